@@ -1,0 +1,1035 @@
+/*
+ * Stratego rules oracle: a plain, slow, scalar CPU implementation of the
+ * batched game engine's semantics (setup, legal moves, uniform move
+ * sampling, move application with battles and history features, terminal
+ * and draw detection, auto-reset, the 488-channel information-state
+ * encoding, and the search-shaped hidden-type resampler).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file exists to check the GPU engine.  Only
+ * the test suite, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no code, header, table or constant generator with the
+ * HIP engine; both sides are written independently from the paper and from
+ * the written readings of it.
+ *
+ * Paper references are to arXiv 2511.07312 ("Superhuman AI for Stratego"):
+ *   App. A  (Rules of Stratego, incl. Table "pieces")
+ *   App. B  (GPU simulator: reset behaviour, API table, auto-reset)
+ *   App. C  (Information state: C.1 board channels 0-455, C.2 recent moves)
+ *   App. D.1 (game-rule hyper-parameters: k-move rule, max game length)
+ *
+ * Pinning status of each part (how the tests tie it to something other
+ * than itself):
+ *   battle outcome ............ pinned: full 10x12 table fixture from Table pieces
+ *   legal moves ............... pinned: brute-force pairwise predicate, closed form at ply 0
+ *   setup shuffle ............. pinned: multiset/row invariants, uniformity test
+ *   Philox4x32-10 ............. pinned: SC'11 known-answer vectors + an independent library
+ *   terminal logic ............ pinned: hand-built positions for every reason
+ *   probability channels ...... pinned: brute-force enumeration of consistent assignments
+ *   history features .......... parity unpinned by the paper (no worked example);
+ *                               checked only by hand-built scenarios derived from
+ *                               the written readings, plus invariants
+ *   encoding layout ........... pinned by invariants and hand-built positions
+ *   resampler ................. pinned by invariants and by agreement of its
+ *                               empirical frequencies with the probability channels
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+
+/* ------------------------------------------------------------------ */
+/* Pieces (App. A, Table "pieces").  Type index follows the channel order
+ * of App. C.1 channels 0-11: Spy, Scout, Miner, Sergeant, Lieutenant,
+ * Captain, Major, Colonel, General, Marshal, Flag, Bomb.                */
+enum { SPY = 0, SCOUT, MINER, SERGEANT, LIEUTENANT, CAPTAIN, MAJOR, COLONEL,
+       GENERAL, MARSHAL, FLAG, BOMB, NUM_TYPES };
+
+static const int INITIAL_COUNT[NUM_TYPES] = {1, 8, 5, 4, 4, 4, 3, 2, 1, 1, 1, 6};
+
+#define NSQ 100
+#define NPIECES 80
+#define NCHAN 488
+#define PLANE 100
+#define MASK_WORDS 157
+#define RING 32
+#define EMPTY (-1)
+#define LAKE (-2)
+
+enum { REASON_NONE = 0, REASON_FLAG = 1, REASON_FORCED_WIN = 2,
+       REASON_FORCED_DRAW = 3, REASON_KMOVE = 4, REASON_MAXMOVES = 5 };
+
+enum { BATTLE_ATTACKER = 0, BATTLE_DEFENDER = 1, BATTLE_TIE = 2 };
+
+enum { TAG_MOVE = 0, TAG_SETUP0 = 1, TAG_SETUP1 = 2, TAG_RESAMPLE = 3 };
+
+typedef struct {
+    uint64_t seed;
+    int32_t k_battleless;   /* k of the k-move rule (App. D.1: 100 in training) */
+    int32_t max_moves;      /* maximum game length (App. D.1: 4000) */
+    int32_t auto_reset;     /* reset terminated games to a fresh setup (App. B) */
+    int32_t pad;
+} orc_cfg;
+
+typedef struct {
+    int type;
+    int alive;
+    int revealed;
+    int moved;
+    int death_square;   /* -1 while alive */
+    int death_cause;    /* 0 while alive, else 1..6 (App. C.1 "Causes of death") */
+    /* "has ever" sets (App. C.1): 11-bit sets, bit i < 10 = revealed type i,
+     * bit 10 = hidden */
+    unsigned threat, evade, adj;
+    /* 13-bit protection sets: bits 0..10 = revealed type (Spy..Marshal, Bomb),
+     * bit 11 = empty square (only for prot) / padding, bit 12 = hidden */
+    unsigned prot, prot_against, been_by, been_against;
+} orc_piece;
+
+typedef struct {
+    uint32_t game_id;
+    uint32_t episode;
+    int ply;            /* moves made in this episode; red acts when even */
+    int battleless;     /* consecutive moves without a battle */
+    int board[NSQ];     /* piece id, EMPTY or LAKE */
+    orc_piece piece[NPIECES];
+    int ring_count;
+    int ring_from[RING];
+    int ring_to[RING];
+    int done;
+    int outcome;
+    int reason;
+    uint32_t redraws;
+} orc_state;
+
+/* ------------------------------------------------------------------ */
+/* Board geometry (App. A: 10x10, 92 occupiable squares, two 2x2 lakes in
+ * the middle rows).  Square index = 10*row + col.                       */
+static int is_lake(int sq) {
+    int r = sq / 10, c = sq % 10;
+    return (r == 4 || r == 5) && (c == 2 || c == 3 || c == 6 || c == 7);
+}
+
+static int owner_of(int id) { return id < 40 ? 0 : 1; }
+
+/* Start square implied by the piece id: red id i starts on square i, blue
+ * id 40+i starts on square 99-i. */
+static int start_square(int id) { return id < 40 ? id : 99 - (id - 40); }
+
+static int is_movable_type(int t) { return t != FLAG && t != BOMB; }
+
+/* On-board orthogonal neighbours, written to nb[]; returns their count. */
+static int neighbours(int sq, int nb[4]) {
+    int r = sq / 10, c = sq % 10, n = 0;
+    if (r > 0) nb[n++] = sq - 10;
+    if (r < 9) nb[n++] = sq + 10;
+    if (c > 0) nb[n++] = sq - 1;
+    if (c < 9) nb[n++] = sq + 1;
+    return n;
+}
+
+static int adjacent(int a, int b) {
+    int ra = a / 10, ca = a % 10, rb = b / 10, cb = b % 10;
+    int dr = ra - rb, dc = ca - cb;
+    if (dr < 0) dr = -dr;
+    if (dc < 0) dc = -dc;
+    return dr + dc == 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Battle outcome (App. A, Table pieces).  Attacker type a is movable.    */
+int orc_battle(int a, int d) {
+    if (d == FLAG) return BATTLE_ATTACKER;                 /* Flag loses to any attacker */
+    if (d == BOMB) return a == MINER ? BATTLE_ATTACKER     /* Miner defeats Bomb */
+                                     : BATTLE_DEFENDER;    /* Bomb defeats other attackers */
+    if (a == SPY && d == MARSHAL) return BATTLE_ATTACKER;  /* Spy defeats Marshal when attacking */
+    /* otherwise by rank: rank = type index + 1 for Spy..Marshal */
+    if (a > d) return BATTLE_ATTACKER;
+    if (a < d) return BATTLE_DEFENDER;
+    return BATTLE_TIE;
+}
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random
+ * numbers: as easy as 1, 2, 3").  Ten rounds of the 4x32 Philox S-box with
+ * a Weyl-sequence key schedule.                                          */
+static void philox_round(uint32_t c[4], const uint32_t k[2]) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c[1] ^ k[0];
+    uint32_t n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(c, k);
+    }
+    memcpy(out, c, sizeof(c));
+}
+
+static void philox_block(uint64_t seed, uint32_t game_id, uint32_t a, uint32_t episode,
+                         uint32_t tag, uint32_t out[4]) {
+    uint32_t ctr[4] = {game_id, a, episode, tag};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Uniform integer in [0, n) from one 32-bit word by multiply-shift. */
+static uint32_t bounded(uint32_t u, uint32_t n) {
+    return (uint32_t)(((uint64_t)u * (uint64_t)n) >> 32);
+}
+
+/* Sequential stream of 32-bit words: block j of a counter supplies words
+ * x, y, z, w in that order. */
+typedef struct {
+    uint64_t seed;
+    uint32_t game_id, episode, tag;
+    uint32_t block;
+    uint32_t words[4];
+    int used;
+} word_stream;
+
+static void stream_init(word_stream* s, uint64_t seed, uint32_t game_id, uint32_t episode,
+                        uint32_t tag) {
+    s->seed = seed;
+    s->game_id = game_id;
+    s->episode = episode;
+    s->tag = tag;
+    s->block = 0;
+    s->used = 4;
+}
+
+static uint32_t stream_next(word_stream* s) {
+    if (s->used == 4) {
+        philox_block(s->seed, s->game_id, s->block, s->episode, s->tag, s->words);
+        s->block++;
+        s->used = 0;
+    }
+    return s->words[s->used++];
+}
+
+/* ------------------------------------------------------------------ */
+/* Legal moves (App. A "Piece details").  legal[100*from+to] = 1.         */
+static int legal_actions(const orc_state* st, int player, unsigned char* legal) {
+    static const int DR[4] = {-1, 1, 0, 0};
+    static const int DC[4] = {0, 0, -1, 1};
+    int n = 0;
+    if (legal) memset(legal, 0, 10000);
+    for (int x = 0; x < NSQ; x++) {
+        int id = st->board[x];
+        if (id < 0 || owner_of(id) != player) continue;
+        int t = st->piece[id].type;
+        if (!is_movable_type(t)) continue;
+        int maxk = (t == SCOUT) ? 9 : 1;
+        for (int d = 0; d < 4; d++) {
+            int r = x / 10, c = x % 10;
+            for (int k = 1; k <= maxk; k++) {
+                int rr = r + DR[d] * k, cc = c + DC[d] * k;
+                if (rr < 0 || rr > 9 || cc < 0 || cc > 9) break;
+                int y = rr * 10 + cc;
+                if (is_lake(y)) break;
+                int o = st->board[y];
+                if (o == EMPTY) {
+                    if (legal) legal[100 * x + y] = 1;
+                    n++;
+                    continue;
+                }
+                if (owner_of(o) != player) {
+                    if (legal) legal[100 * x + y] = 1;
+                    n++;
+                }
+                break;
+            }
+        }
+    }
+    return n;
+}
+
+/* A player has a legal move iff one of its movable pieces has an adjacent
+ * square that is empty or holds an enemy piece (a Scout's longer moves
+ * always pass through such an adjacent empty square). */
+static int has_legal_move(const orc_state* st, int player) {
+    return legal_actions(st, player, NULL) > 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Terminal check (App. A game summary, App. D.1 rule parameters).  The
+ * priority order is a reading: flag capture, then no legal moves, then the
+ * k-move rule, then the maximum length. */
+static void terminal_check(orc_state* st, const orc_cfg* cfg, int flag_captured_by) {
+    int q = st->ply & 1;
+    if (flag_captured_by >= 0) {
+        st->done = 1;
+        st->outcome = flag_captured_by == 0 ? 1 : -1;
+        st->reason = REASON_FLAG;
+        return;
+    }
+    if (!has_legal_move(st, q)) {
+        st->done = 1;
+        if (!has_legal_move(st, 1 - q)) {
+            st->outcome = 0;
+            st->reason = REASON_FORCED_DRAW;
+        } else {
+            st->outcome = (1 - q) == 0 ? 1 : -1;
+            st->reason = REASON_FORCED_WIN;
+        }
+        return;
+    }
+    if (st->battleless >= cfg->k_battleless) {
+        st->done = 1;
+        st->outcome = 0;
+        st->reason = REASON_KMOVE;
+        return;
+    }
+    if (st->ply >= cfg->max_moves) {
+        st->done = 1;
+        st->outcome = 0;
+        st->reason = REASON_MAXMOVES;
+        return;
+    }
+    st->done = 0;
+    st->outcome = 0;
+    st->reason = REASON_NONE;
+}
+
+/* ------------------------------------------------------------------ */
+/* Setup: each player's 40 pieces uniformly at random in its own four back
+ * rows (App. A), drawn by a Durstenfeld shuffle of the type multiset. */
+static void shuffle_setup(uint64_t seed, uint32_t game_id, uint32_t episode, int player,
+                          int types_out[40]) {
+    int a[40], n = 0;
+    for (int t = 0; t < NUM_TYPES; t++)
+        for (int c = 0; c < INITIAL_COUNT[t]; c++) a[n++] = t;
+    word_stream ws;
+    stream_init(&ws, seed, game_id, episode, player == 0 ? TAG_SETUP0 : TAG_SETUP1);
+    for (int i = 39; i >= 1; i--) {
+        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));
+        int tmp = a[i];
+        a[i] = a[j];
+        a[j] = tmp;
+    }
+    memcpy(types_out, a, sizeof(a));
+}
+
+static void fresh_state(orc_state* st, uint64_t seed, uint32_t game_id, uint32_t episode) {
+    uint32_t redraws = st->redraws;
+    memset(st, 0, sizeof(*st));
+    st->redraws = redraws;
+    st->game_id = game_id;
+    st->episode = episode;
+    for (int s = 0; s < NSQ; s++) st->board[s] = is_lake(s) ? LAKE : EMPTY;
+    for (int p = 0; p < 2; p++) {
+        int types[40];
+        shuffle_setup(seed, game_id, episode, p, types);
+        for (int slot = 0; slot < 40; slot++) {
+            int id = p * 40 + slot;
+            int sq = p == 0 ? slot : 99 - slot;
+            orc_piece* pc = &st->piece[id];
+            memset(pc, 0, sizeof(*pc));
+            pc->type = types[slot];
+            pc->alive = 1;
+            pc->death_square = -1;
+            st->board[sq] = id;
+        }
+    }
+}
+
+/* Fresh game for (game_id, episode); with auto-reset a setup that is
+ * already terminal is replaced by the next episode's setup. */
+static void reset_game(orc_state* st, const orc_cfg* cfg, uint32_t game_id, uint32_t episode) {
+    fresh_state(st, cfg->seed, game_id, episode);
+    terminal_check(st, cfg, -1);
+    while (st->done && cfg->auto_reset) {
+        st->redraws++;
+        fresh_state(st, cfg->seed, game_id, st->episode + 1);
+        terminal_check(st, cfg, -1);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+static unsigned hidden_or_type10(const orc_piece* p) {
+    /* channel slot for threat/evade/adjacency targets: revealed Spy..Marshal -> type,
+     * hidden -> 10 */
+    return p->revealed ? (unsigned)p->type : 10u;
+}
+
+static unsigned hidden_or_type11(const orc_piece* p) {
+    /* protection slots: revealed Spy..Marshal -> 0..9, revealed Bomb -> 10, hidden -> 12 */
+    if (!p->revealed) return 12u;
+    return p->type == BOMB ? 10u : (unsigned)p->type;
+}
+
+/* Move application with battle resolution and the history features of
+ * App. C.1 (threats, evasions, active adjacency, deaths, protection).
+ * Returns 1 if the action was applied, 0 if it was not legal. */
+static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
+    if (action < 0 || action >= 10000) return 0;
+    int from = action / 100, to = action % 100;
+    int p = st->ply & 1, q = 1 - p;
+    unsigned char legal[10000];
+    legal_actions(st, p, legal);
+    if (!legal[action]) return 0;
+
+    int X = st->board[from];
+
+    /* previous move, if any: its mover A and destination a */
+    int A = -1, a = -1, prev_was_threat = 0;
+    if (st->ring_count > 0) {
+        int slot = (st->ply - 1) & (RING - 1);
+        int pt = st->ring_to[slot];
+        int id = st->board[pt];
+        if (id >= 0 && owner_of(id) == q) {
+            A = id;
+            a = pt;
+            int nb[4], nn = neighbours(a, nb);
+            for (int i = 0; i < nn; i++) {
+                int o = st->board[nb[i]];
+                if (o >= 0 && owner_of(o) == p) prev_was_threat = 1;
+            }
+        }
+    }
+
+    /* 1. active adjacency, evaluated before the move: every movable piece of
+     *    p adjacent to an enemy piece it could have attacked but did not */
+    for (int x = 0; x < NSQ; x++) {
+        int id = st->board[x];
+        if (id < 0 || owner_of(id) != p) continue;
+        if (!is_movable_type(st->piece[id].type)) continue;
+        int nb[4], nn = neighbours(x, nb);
+        for (int i = 0; i < nn; i++) {
+            int y = nb[i];
+            int e = st->board[y];
+            if (e < 0 || owner_of(e) != q) continue;
+            if (x == from && y == to) continue;
+            const orc_piece* Y = &st->piece[e];
+            if (Y->revealed && !is_movable_type(Y->type)) continue;
+            st->piece[id].adj |= 1u << hidden_or_type10(Y);
+        }
+    }
+
+    /* 2. evasion: the mover was threatened by A on the previous move and now
+     *    moves to an empty square that is not adjacent to A */
+    int target = st->board[to];
+    if (A >= 0 && adjacent(from, a) && target == EMPTY && !adjacent(to, a))
+        st->piece[X].evade |= 1u << hidden_or_type10(&st->piece[A]);
+
+    /* 3. resolve the move or battle */
+    int battle = target >= 0;
+    int flag_captured_by = -1;
+    int attacker_alive = 1;
+    if (!battle) {
+        st->board[to] = X;
+        st->board[from] = EMPTY;
+    } else {
+        int Y = target;
+        orc_piece* px = &st->piece[X];
+        orc_piece* py = &st->piece[Y];
+        int rY = py->revealed;
+        int res = orc_battle(px->type, py->type);
+        px->revealed = 1;
+        py->revealed = 1;
+        if (py->type == FLAG) flag_captured_by = p;
+        st->board[from] = EMPTY;
+        if (res == BATTLE_ATTACKER) {
+            st->board[to] = X;
+            py->alive = 0;
+            py->death_square = to;
+            py->death_cause = !rY ? 6 : 4;
+        } else if (res == BATTLE_DEFENDER) {
+            attacker_alive = 0;
+            px->alive = 0;
+            px->death_square = to;
+            px->death_cause = !rY ? 3 : 1;
+        } else {
+            attacker_alive = 0;
+            st->board[to] = EMPTY;
+            px->alive = 0;
+            px->death_square = to;
+            px->death_cause = !rY ? 3 : 2;
+            py->alive = 0;
+            py->death_square = to;
+            py->death_cause = !rY ? 6 : 5;
+        }
+    }
+    st->piece[X].moved = 1;
+
+    /* 5. threats made by the move: the mover, if it stands on `to`, against
+     *    every adjacent enemy piece */
+    if (attacker_alive) {
+        int nb[4], nn = neighbours(to, nb);
+        for (int i = 0; i < nn; i++) {
+            int e = st->board[nb[i]];
+            if (e < 0 || owner_of(e) != q) continue;
+            const orc_piece* Y = &st->piece[e];
+            if (Y->revealed && !is_movable_type(Y->type)) continue;
+            st->piece[X].threat |= 1u << hidden_or_type10(Y);
+        }
+    }
+
+    /* 6. protection: a non-battle reply to a threat by A, in which the mover
+     *    becomes adjacent to a square next to A */
+    if (!battle && A >= 0 && prev_was_threat) {
+        int nb[4], nn = neighbours(a, nb);
+        for (int i = 0; i < nn; i++) {
+            int s = nb[i];
+            if (is_lake(s)) continue;
+            if (!adjacent(s, to)) continue;
+            if (s == from || adjacent(s, from)) continue;
+            int o = st->board[s];
+            const orc_piece* pa = &st->piece[A];
+            if (o >= 0 && owner_of(o) == p) {
+                orc_piece* pc = &st->piece[X];
+                orc_piece* pb = &st->piece[o];
+                pc->prot |= 1u << hidden_or_type11(pb);
+                pc->prot_against |= 1u << hidden_or_type11(pa);
+                pb->been_by |= 1u << hidden_or_type11(pc);
+                pb->been_against |= 1u << hidden_or_type11(pa);
+            } else if (o == EMPTY) {
+                st->piece[X].prot |= 1u << 11;
+                st->piece[X].prot_against |= 1u << hidden_or_type11(pa);
+            }
+        }
+    }
+
+    /* 7-8. move history and counters */
+    int slot = st->ply & (RING - 1);
+    st->ring_from[slot] = from;
+    st->ring_to[slot] = to;
+    if (st->ring_count < RING) st->ring_count++;
+    st->ply += 1;
+    st->battleless = battle ? 0 : st->battleless + 1;
+
+    terminal_check(st, cfg, flag_captured_by);
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Probability channels (App. C.1 channels 12-35): the chance that a hidden
+ * piece of player w has type T when the hidden types are a uniformly random
+ * assignment of w's remaining type multiset, constrained only by "a piece
+ * that has moved is neither Flag nor Bomb".  Returned as an exact rational. */
+typedef struct {
+    int n[NUM_TYPES];   /* hidden multiset */
+    int H, I, M, U;
+} hidden_stats;
+
+static void compute_hidden_stats(const orc_state* st, int w, hidden_stats* hs) {
+    memset(hs, 0, sizeof(*hs));
+    for (int t = 0; t < NUM_TYPES; t++) hs->n[t] = INITIAL_COUNT[t];
+    for (int id = w * 40; id < w * 40 + 40; id++) {
+        const orc_piece* p = &st->piece[id];
+        if (!p->alive || p->revealed) {
+            hs->n[p->type]--;           /* known type: revealed or dead */
+        } else {
+            hs->H++;
+            if (p->moved) hs->M++;
+        }
+    }
+    hs->I = hs->n[FLAG] + hs->n[BOMB];
+    hs->U = hs->H - hs->M;
+}
+
+static void hidden_prob(const hidden_stats* hs, int moved, int t, long* num, long* den) {
+    int movable_slots = hs->H - hs->I;
+    if (moved) {
+        if (!is_movable_type(t)) { *num = 0; *den = 1; return; }
+        *num = hs->n[t];
+        *den = movable_slots;
+        return;
+    }
+    if (!is_movable_type(t)) {
+        *num = hs->n[t];
+        *den = hs->U;
+        return;
+    }
+    *num = (long)hs->n[t] * (hs->U - hs->I);
+    *den = (long)hs->U * movable_slots;
+}
+
+/* round-half-up of 255*num/den, 0 when den == 0 */
+static int quant255(long num, long den) {
+    if (den == 0) return 0;
+    return (int)((510 * num + den) / (2 * den));
+}
+
+/* exported for tests: exact probability numerator/denominator for a hidden
+ * piece of player w with the given moved flag and candidate type */
+void orc_hidden_prob(const orc_state* st, int w, int moved, int t, long* num, long* den) {
+    hidden_stats hs;
+    compute_hidden_stats(st, w, &hs);
+    hidden_prob(&hs, moved, t, num, den);
+}
+
+/* ------------------------------------------------------------------ */
+/* Information state of observer o (App. C): 456 board channels followed by
+ * 32 recent-move channels, each a 10x10 plane in the observer's frame
+ * (blue's view is the board rotated by 180 degrees).  uint8 values:
+ * indicators are 1, probabilities and fractions are round(255*x), and move
+ * planes hold +1 (0x01) at the destination and -1 (0xFF) at the source. */
+static int frame(int o, int sq) { return o == 0 ? sq : 99 - sq; }
+
+static void put(uint8_t* out, int ch, int sq_frame, uint8_t v) {
+    out[ch * PLANE + sq_frame] = v;
+}
+
+static void encode(const orc_state* st, const orc_cfg* cfg, int o, uint8_t* out) {
+    int z = 1 - o;
+    memset(out, 0, NCHAN * PLANE);
+    hidden_stats hs_own, hs_opp;
+    compute_hidden_stats(st, o, &hs_own);
+    compute_hidden_stats(st, z, &hs_opp);
+
+    for (int s = 0; s < NSQ; s++) {
+        int f = frame(o, s);
+        int id = st->board[s];
+        if (id == LAKE) continue;
+        if (id == EMPTY) {
+            put(out, 38, f, 1);                                     /* 38: empty */
+            continue;
+        }
+        const orc_piece* P = &st->piece[id];
+        int own = owner_of(id) == o;
+        if (own) {
+            put(out, P->type, f, 1);                                /* 0-11: own type */
+            if (!P->revealed) put(out, 36, f, 1);                   /* 36: own hidden */
+            if (P->moved) put(out, 39, f, 1);                       /* 39: own moved */
+        } else {
+            if (!P->revealed) put(out, 37, f, 1);                   /* 37: opponent hidden */
+            if (P->moved) put(out, 40, f, 1);                       /* 40: opponent moved */
+        }
+        /* 12-23 (about the opponent's pieces) and 24-35 (about own pieces, from
+         * the opponent's point of view) */
+        int pbase = own ? 24 : 12;
+        const hidden_stats* hs = own ? &hs_own : &hs_opp;
+        if (P->revealed) {
+            put(out, pbase + P->type, f, 255);
+        } else {
+            for (int t = 0; t < NUM_TYPES; t++) {
+                long num, den;
+                hidden_prob(hs, P->moved, t, &num, &den);
+                put(out, pbase + t, f, (uint8_t)quant255(num, den));
+            }
+        }
+        /* 43-75 own / 76-108 opponent: threat, evasion, active adjacency */
+        int hbase = own ? 43 : 76;
+        for (int j = 0; j < 11; j++) {
+            if (P->threat & (1u << j)) put(out, hbase + j, f, 1);
+            if (P->evade & (1u << j)) put(out, hbase + 11 + j, f, 1);
+            if (P->adj & (1u << j)) put(out, hbase + 22 + j, f, 1);
+        }
+        /* 251-302 own / 303-354 opponent: protection groups of 13 */
+        int gbase = own ? 251 : 303;
+        for (int j = 0; j < 13; j++) {
+            if (P->prot & (1u << j)) put(out, gbase + j, f, 1);
+            if (P->prot_against & (1u << j)) put(out, gbase + 13 + j, f, 1);
+            if (P->been_by & (1u << j)) put(out, gbase + 26 + j, f, 1);
+            if (P->been_against & (1u << j)) put(out, gbase + 39 + j, f, 1);
+        }
+        /* 355-454: start square of the piece on this square */
+        put(out, 355 + frame(o, start_square(id)), f, 1);
+    }
+
+    /* 41-42: fraction of the move budget and of the k-move budget used */
+    int v41 = quant255(st->ply, cfg->max_moves);
+    int v42 = quant255(st->battleless, cfg->k_battleless);
+    for (int f = 0; f < NSQ; f++) {
+        put(out, 41, f, (uint8_t)v41);
+        put(out, 42, f, (uint8_t)v42);
+    }
+
+    /* 109-250: captured pieces by start square and by death square x cause */
+    for (int id = 0; id < NPIECES; id++) {
+        const orc_piece* P = &st->piece[id];
+        if (P->alive) continue;
+        int own = owner_of(id) == o;
+        int t = P->type;
+        if (t == FLAG) continue;
+        int slot11 = t == BOMB ? 10 : t;
+        put(out, (own ? 109 : 120) + slot11, frame(o, start_square(id)), 1);
+        if (t <= MARSHAL)
+            put(out, (own ? 131 : 191) + 10 * (P->death_cause - 1) + t,
+                frame(o, P->death_square), 1);
+    }
+
+    /* 456-487: the last 32 moves, most recent first (App. C.2) */
+    for (int i = 0; i < st->ring_count && i < RING; i++) {
+        int slot = (st->ply - 1 - i) & (RING - 1);
+        put(out, 456 + i, frame(o, st->ring_to[slot]), 0x01);
+        put(out, 456 + i, frame(o, st->ring_from[slot]), 0xFF);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Canonical state record: 1536 bytes, little-endian (layout written out in
+ * the project documentation; serialised here independently). */
+#define REC_BYTES 1536
+
+static void put_u32(uint8_t* b, int off, uint32_t v) {
+    b[off] = (uint8_t)v;
+    b[off + 1] = (uint8_t)(v >> 8);
+    b[off + 2] = (uint8_t)(v >> 16);
+    b[off + 3] = (uint8_t)(v >> 24);
+}
+
+static uint32_t get_u32(const uint8_t* b, int off) {
+    return (uint32_t)b[off] | ((uint32_t)b[off + 1] << 8) | ((uint32_t)b[off + 2] << 16) |
+           ((uint32_t)b[off + 3] << 24);
+}
+
+static void to_record(const orc_state* st, uint8_t* rec) {
+    memset(rec, 0, REC_BYTES);
+    put_u32(rec, 0, st->game_id);
+    put_u32(rec, 4, st->episode);
+    put_u32(rec, 8, (uint32_t)st->ply);
+    put_u32(rec, 12, (uint32_t)st->battleless);
+    rec[16] = (uint8_t)st->ring_count;
+    rec[17] = (uint8_t)st->done;
+    rec[18] = (uint8_t)(int8_t)st->outcome;
+    rec[19] = (uint8_t)st->reason;
+    put_u32(rec, 20, st->redraws);
+    for (int s = 0; s < NSQ; s++) rec[64 + s] = (uint8_t)(int8_t)st->board[s];
+    for (int m = 0; m < RING; m++) {
+        rec[164 + 2 * m] = (uint8_t)st->ring_from[m];
+        rec[164 + 2 * m + 1] = (uint8_t)st->ring_to[m];
+    }
+    for (int id = 0; id < NPIECES; id++) {
+        const orc_piece* p = &st->piece[id];
+        uint32_t w0 = (uint32_t)p->type | ((uint32_t)p->alive << 4) |
+                      ((uint32_t)p->revealed << 5) | ((uint32_t)p->moved << 6) |
+                      ((uint32_t)p->death_cause << 7) |
+                      ((uint32_t)(p->alive ? 127 : p->death_square) << 10) |
+                      ((uint32_t)p->been_against << 17);
+        uint32_t w1 = p->threat | (p->evade << 11);
+        uint32_t w2 = p->adj | (p->prot << 11);
+        uint32_t w3 = p->prot_against | (p->been_by << 13);
+        int off = 256 + 16 * id;
+        put_u32(rec, off, w0);
+        put_u32(rec, off + 4, w1);
+        put_u32(rec, off + 8, w2);
+        put_u32(rec, off + 12, w3);
+    }
+}
+
+static void from_record(orc_state* st, const uint8_t* rec) {
+    memset(st, 0, sizeof(*st));
+    st->game_id = get_u32(rec, 0);
+    st->episode = get_u32(rec, 4);
+    st->ply = (int)get_u32(rec, 8);
+    st->battleless = (int)get_u32(rec, 12);
+    st->ring_count = rec[16];
+    st->done = rec[17];
+    st->outcome = (int8_t)rec[18];
+    st->reason = rec[19];
+    st->redraws = get_u32(rec, 20);
+    for (int s = 0; s < NSQ; s++) st->board[s] = (int8_t)rec[64 + s];
+    for (int m = 0; m < RING; m++) {
+        st->ring_from[m] = rec[164 + 2 * m];
+        st->ring_to[m] = rec[164 + 2 * m + 1];
+    }
+    for (int id = 0; id < NPIECES; id++) {
+        int off = 256 + 16 * id;
+        uint32_t w0 = get_u32(rec, off), w1 = get_u32(rec, off + 4);
+        uint32_t w2 = get_u32(rec, off + 8), w3 = get_u32(rec, off + 12);
+        orc_piece* p = &st->piece[id];
+        p->type = (int)(w0 & 15);
+        p->alive = (int)((w0 >> 4) & 1);
+        p->revealed = (int)((w0 >> 5) & 1);
+        p->moved = (int)((w0 >> 6) & 1);
+        p->death_cause = (int)((w0 >> 7) & 7);
+        int dsq = (int)((w0 >> 10) & 127);
+        p->death_square = p->alive ? -1 : dsq;
+        p->been_against = (w0 >> 17) & 0x1FFF;
+        p->threat = w1 & 0x7FF;
+        p->evade = (w1 >> 11) & 0x7FF;
+        p->adj = w2 & 0x7FF;
+        p->prot = (w2 >> 11) & 0x1FFF;
+        p->prot_against = w3 & 0x1FFF;
+        p->been_by = (w3 >> 13) & 0x1FFF;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Search-shaped resampling: draw the hidden types of player z uniformly
+ * among assignments consistent with public information (revealed and dead
+ * pieces known; a piece that moved is neither Flag nor Bomb).  Stands in
+ * for the belief-model samples that search materialises on device (paper
+ * section 2.5 and App. B reset behaviour). */
+static void resample(const orc_state* src, orc_state* dst, uint64_t seed, uint32_t new_game_id) {
+    *dst = *src;
+    dst->game_id = new_game_id;
+    int z = 1 - (src->ply & 1);
+    hidden_stats hs;
+    compute_hidden_stats(src, z, &hs);
+    int unmoved[40], nu = 0;
+    int assigned[NPIECES];
+    for (int i = 0; i < NPIECES; i++) assigned[i] = -1;
+    for (int id = z * 40; id < z * 40 + 40; id++) {
+        const orc_piece* p = &src->piece[id];
+        if (p->alive && !p->revealed && !p->moved) unmoved[nu++] = id;
+    }
+    word_stream ws;
+    stream_init(&ws, seed, new_game_id, src->episode, TAG_RESAMPLE);
+    /* step 1: positions of the hidden Flag and Bombs among unmoved pieces */
+    int I = hs.I;
+    for (int i = 0; i < I; i++) {
+        int j = i + (int)bounded(stream_next(&ws), (uint32_t)(nu - i));
+        int tmp = unmoved[i];
+        unmoved[i] = unmoved[j];
+        unmoved[j] = tmp;
+    }
+    for (int i = 0; i < I; i++) assigned[unmoved[i]] = (i < hs.n[FLAG]) ? FLAG : BOMB;
+    /* step 2: the movable multiset shuffled over the remaining hidden pieces
+     * in ascending id order */
+    int list[40], L = 0;
+    for (int t = 0; t <= MARSHAL; t++)
+        for (int c = 0; c < hs.n[t]; c++) list[L++] = t;
+    for (int i = L - 1; i >= 1; i--) {
+        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));
+        int tmp = list[i];
+        list[i] = list[j];
+        list[j] = tmp;
+    }
+    int k = 0;
+    for (int id = z * 40; id < z * 40 + 40; id++) {
+        const orc_piece* p = &src->piece[id];
+        if (!p->alive || p->revealed) continue;
+        if (assigned[id] >= 0) continue;
+        assigned[id] = list[k++];
+    }
+    for (int id = z * 40; id < z * 40 + 40; id++)
+        if (assigned[id] >= 0) dst->piece[id].type = assigned[id];
+}
+
+/* ------------------------------------------------------------------ */
+/* Batch entry points (games are independent; OpenMP over games). */
+size_t orc_state_bytes(void) { return sizeof(orc_state); }
+int orc_record_bytes(void) { return REC_BYTES; }
+
+void orc_batch_reset(orc_state* s, int n, const orc_cfg* cfg, const uint32_t* game_ids) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++) {
+        s[i].redraws = 0;
+        reset_game(&s[i], cfg, game_ids[i], 0);
+    }
+}
+
+static int mask_one(const orc_state* st, uint64_t* mask) {
+    unsigned char legal[10000];
+    memset(mask, 0, MASK_WORDS * sizeof(uint64_t));
+    if (st->done) return 0;
+    int n = legal_actions(st, st->ply & 1, legal);
+    for (int a = 0; a < 10000; a++)
+        if (legal[a]) mask[a >> 6] |= (uint64_t)1 << (a & 63);
+    return n;
+}
+
+void orc_batch_mask(const orc_state* s, int n, uint64_t* mask, int16_t* num_legal) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++) {
+        int c = mask_one(&s[i], mask + (size_t)i * MASK_WORDS);
+        if (num_legal) num_legal[i] = (int16_t)c;
+    }
+}
+
+/* Uniform legal action (App. B "SampleRandomLegalAction"): the r-th legal
+ * action in ascending id order, r = bounded(Philox(seed; game, ply,
+ * episode, MOVE).x, n). */
+static int sample_one(const orc_state* st, uint64_t seed, const uint64_t* mask, int n) {
+    if (n <= 0 || st->done) return -1;
+    uint32_t w[4];
+    philox_block(seed, st->game_id, (uint32_t)st->ply, st->episode, TAG_MOVE, w);
+    int r = (int)bounded(w[0], (uint32_t)n);
+    for (int a = 0; a < 10000; a++) {
+        if (mask[a >> 6] & ((uint64_t)1 << (a & 63))) {
+            if (r == 0) return a;
+            r--;
+        }
+    }
+    return -1;
+}
+
+void orc_batch_sample(const orc_state* s, int n, const orc_cfg* cfg, const uint64_t* mask,
+                      const int16_t* num_legal, int16_t* actions) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++)
+        actions[i] = (int16_t)sample_one(&s[i], cfg->seed, mask + (size_t)i * MASK_WORDS,
+                                         num_legal[i]);
+}
+
+/* Step one game.  Output convention: done=1 with the finished episode's
+ * outcome, reason and length when the game is (or becomes) terminal;
+ * zeros otherwise.  Returns 0 on success, -1 for an illegal action. */
+static int step_one(orc_state* st, const orc_cfg* cfg, int action, int8_t* done,
+                    int8_t* outcome, uint8_t* reason, int16_t* ep_len) {
+    if (st->done) {
+        /* already terminal before this call: report it; with auto-reset the
+         * game restarts with the next episode */
+        *done = 1;
+        *outcome = (int8_t)st->outcome;
+        *reason = (uint8_t)st->reason;
+        *ep_len = (int16_t)st->ply;
+        if (cfg->auto_reset) reset_game(st, cfg, st->game_id, st->episode + 1);
+        return 0;
+    }
+    if (action == -1) {
+        *done = 0;
+        *outcome = 0;
+        *reason = 0;
+        *ep_len = 0;
+        return 0;
+    }
+    if (!apply_action(st, cfg, action)) {
+        *done = 0;
+        *outcome = 0;
+        *reason = 0;
+        *ep_len = 0;
+        return -1;
+    }
+    if (st->done) {
+        *done = 1;
+        *outcome = (int8_t)st->outcome;
+        *reason = (uint8_t)st->reason;
+        *ep_len = (int16_t)st->ply;
+        if (cfg->auto_reset) reset_game(st, cfg, st->game_id, st->episode + 1);
+    } else {
+        *done = 0;
+        *outcome = 0;
+        *reason = 0;
+        *ep_len = 0;
+    }
+    return 0;
+}
+
+int orc_batch_step(orc_state* s, int n, const orc_cfg* cfg, const int16_t* actions,
+                   int8_t* done, int8_t* outcome, uint8_t* reason, int16_t* ep_len) {
+    int first_bad = -1;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++) {
+        if (step_one(&s[i], cfg, actions[i], &done[i], &outcome[i], &reason[i], &ep_len[i]) != 0) {
+#pragma omp critical
+            {
+                if (first_bad < 0 || i < first_bad) first_bad = i;
+            }
+        }
+    }
+    return first_bad;
+}
+
+void orc_batch_encode(const orc_state* s, int n, const orc_cfg* cfg, uint8_t* obs) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < n; i++)
+        for (int o = 0; o < 2; o++)
+            encode(&s[i], cfg, o, obs + ((size_t)i * 2 + o) * NCHAN * PLANE);
+}
+
+/* Encode only selected games (index list) into a compact output. */
+void orc_batch_encode_subset(const orc_state* s, const int32_t* idx, int m, const orc_cfg* cfg,
+                             uint8_t* obs) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < m; i++)
+        for (int o = 0; o < 2; o++)
+            encode(&s[idx[i]], cfg, o, obs + ((size_t)i * 2 + o) * NCHAN * PLANE);
+}
+
+void orc_batch_export(const orc_state* s, int n, uint8_t* rec) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++) to_record(&s[i], rec + (size_t)i * REC_BYTES);
+}
+
+void orc_batch_import(orc_state* s, int n, const uint8_t* rec) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++) from_record(&s[i], rec + (size_t)i * REC_BYTES);
+}
+
+/* dst[i*per + j] = resample of src[i] with game id base + i*per + j */
+void orc_batch_resample(const orc_state* src, int nsrc, int per, uint64_t seed,
+                        uint32_t game_id_base, orc_state* dst) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int k = 0; k < nsrc * per; k++) {
+        int i = k / per;
+        resample(&src[i], &dst[k], seed, game_id_base + (uint32_t)k);
+    }
+}
+
+/* One whole ply of the fused engine for every game: mask, sample, encode
+ * both observers (of the pre-move state), then step with the configured
+ * auto-reset.  Any output pointer may be NULL. */
+void orc_batch_ply(orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int16_t* num_legal,
+                   int16_t* actions, uint8_t* obs, int8_t* done, int8_t* outcome,
+                   uint8_t* reason, int16_t* ep_len) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < n; i++) {
+        uint64_t m[MASK_WORDS];
+        int c = mask_one(&s[i], m);
+        int a = sample_one(&s[i], cfg->seed, m, c);
+        if (mask) memcpy(mask + (size_t)i * MASK_WORDS, m, sizeof(m));
+        if (num_legal) num_legal[i] = (int16_t)c;
+        if (actions) actions[i] = (int16_t)a;
+        if (obs)
+            for (int o = 0; o < 2; o++)
+                encode(&s[i], cfg, o, obs + ((size_t)i * 2 + o) * NCHAN * PLANE);
+        int8_t d, oc;
+        uint8_t r;
+        int16_t el;
+        step_one(&s[i], cfg, a, &d, &oc, &r, &el);
+        if (done) done[i] = d;
+        if (outcome) outcome[i] = oc;
+        if (reason) reason[i] = r;
+        if (ep_len) ep_len[i] = el;
+    }
+}
+
+/* Single-game helpers for tests. */
+int orc_legal_list(const orc_state* st, int player, unsigned char* legal10000) {
+    return legal_actions(st, player, legal10000);
+}
+
+int orc_has_legal_move(const orc_state* st, int player) { return has_legal_move(st, player); }
+
+void orc_terminal_check(orc_state* st, const orc_cfg* cfg) { terminal_check(st, cfg, -1); }
+
+void orc_setup_types(uint64_t seed, uint32_t game_id, uint32_t episode, int player,
+                     int32_t* types40) {
+    int t[40];
+    shuffle_setup(seed, game_id, episode, player, t);
+    for (int i = 0; i < 40; i++) types40[i] = t[i];
+}
+
+/* 64-bit FNV-1a over a byte buffer (used to compare large outputs). */
+uint64_t orc_fnv1a64(const uint8_t* buf, size_t len) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < len; i++) {
+        h ^= buf[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+/* Human-readable board (App. B "BoardStrs" debugging aid): rows 9..0 top to
+ * bottom, three characters per square: owner ('r'/'b') and type symbol
+ * (S 2-9 M F B), "~~" lake, ".." empty. */
+void orc_board_string(const orc_state* st, char* out /* >= 311 bytes */) {
+    static const char SYM[NUM_TYPES] = {'S', '2', '3', '4', '5', '6', '7', '8', '9', 'M', 'F', 'B'};
+    int k = 0;
+    for (int r = 9; r >= 0; r--) {
+        for (int c = 0; c < 10; c++) {
+            int id = st->board[r * 10 + c];
+            if (id == LAKE) { out[k++] = '~'; out[k++] = '~'; }
+            else if (id == EMPTY) { out[k++] = '.'; out[k++] = '.'; }
+            else { out[k++] = owner_of(id) == 0 ? 'r' : 'b'; out[k++] = SYM[st->piece[id].type]; }
+            out[k++] = c == 9 ? '\n' : ' ';
+        }
+    }
+    out[k] = 0;
+}
