@@ -1,0 +1,189 @@
+/*
+ * stratego.h - C ABI of the MI355X batched Stratego engine (libstratego.so).
+ *
+ * The engine advances N independent games of Stratego in lockstep on one GPU:
+ * legal-move masks, uniform random move sampling, move application with battle
+ * resolution, terminal and draw detection with optional auto-reset, and the
+ * 488-channel information-state encoding of both players.  It follows the
+ * paper's simulator description (arXiv 2511.07312, App. B: a single object over
+ * N parallel games, ApplyActions over a tensor of N actions, independent reset
+ * of terminated games, reset to non-initial states for search, no allocation
+ * after construction) and its statement of the game (App. A) and infostate
+ * (App. C).
+ *
+ * Conventions shared by every call
+ *   - Squares are 10*row + col, 0..99.  Red (player 0) starts in rows 0-3 and
+ *     moves first; blue (player 1) starts in rows 6-9.  Lakes are the 2x2
+ *     blocks rows 4-5 x cols 2-3 and 6-7.
+ *   - An action is 100*from + to in absolute squares (0..9999); -1 = no-op.
+ *   - Masks are packed bitsets: uint64 mask[N][157], bit a of game g is
+ *     (mask[g][a >> 6] >> (a & 63)) & 1; bits 10000..10047 are zero.
+ *   - Observations are uint8 obs[N][2][488][10][10]: game, observer (0 red,
+ *     1 blue), channel, row, col, in the observer's frame (blue's view is the
+ *     board rotated by 180 degrees).  Indicator channels hold 1; channels
+ *     12-35 and 41-42 hold round(255*x) of a probability or fraction; channels
+ *     456-487 hold 0x01 at a move's destination and 0xFF (int8 -1) at its
+ *     source (App. C).
+ *   - A game state is a canonical 1536-byte record (layout in the project
+ *     documentation); records are the checkpoint format: importing an exported
+ *     record continues the game bit-exactly.
+ *   - Every device pointer must be device memory on the context's device.
+ *     The caller owns all buffers it passes; the library owns the game states
+ *     (allocated once in stratego_init).
+ *   - Every call is asynchronous on the HIP stream given at init, except
+ *     stratego_get_error, stratego_autotune and stratego_destroy, which
+ *     synchronise it.
+ *   - Return value: STRATEGO_OK (0) or a negative error code.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef STRATEGO_H
+#define STRATEGO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STRATEGO_OK 0
+#define STRATEGO_E_INVAL (-1)          /* bad argument (null pointer, size, range) */
+#define STRATEGO_E_NOMEM (-2)          /* device allocation failed in stratego_init */
+#define STRATEGO_E_HIP (-3)            /* a HIP runtime call failed */
+#define STRATEGO_E_ILLEGAL_ACTION (-4) /* a live game received an illegal action */
+#define STRATEGO_E_BAD_STATE (-5)      /* an imported record is malformed */
+
+#define STRATEGO_NUM_CHANNELS 488
+#define STRATEGO_MASK_WORDS 157
+#define STRATEGO_RECORD_BYTES 1536
+#define STRATEGO_OBS_BYTES_PER_GAME 97600
+
+typedef struct stratego_ctx stratego_ctx;
+
+typedef struct {
+  int32_t num_games;      /* N, fixed for the life of the context */
+  int32_t k_battleless;   /* draw after k consecutive battleless moves (App. D.1: 100) */
+  int32_t max_moves;      /* draw at this many moves (App. D.1: 4000), >= 1 */
+  int32_t auto_reset;     /* 1: a terminated game restarts with a fresh setup (App. B) */
+  uint64_t seed;          /* Philox4x32-10 key for setups, moves and resampling */
+  uint32_t game_id_base;  /* global game id of slot 0; slot i has id base + i */
+  int32_t games_per_wg;   /* fused engine tile size G in {1,2,4,8,16}; 0 = default */
+  int32_t lds_segments;   /* obs image staged in S LDS segments, S in {1,2,4,8}; 0 = default */
+  int32_t reserved;
+} stratego_config;
+
+/* Create a context with N games, all reset to fresh setups (episode 0).
+ * hip_stream: a hipStream_t (NULL = the null stream).  Allocates every device
+ * buffer the context will use.  Errors: E_INVAL, E_NOMEM, E_HIP. */
+int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** out);
+
+/* Reset games (App. B: reset of terminated games; reset to a non-initial state
+ * for search).  slots_dev: int32[n] slot indices, or NULL for slots 0..n-1.
+ * states_dev: NULL = fresh uniform setups with episode 0 (a setup that is
+ * already terminal is redrawn when auto_reset is on); otherwise n canonical
+ * records copied into the slots.  A malformed record (see the record checks in
+ * the project documentation) or a slot outside [0, N) latches E_BAD_STATE in
+ * the error word (see stratego_get_error) and leaves that slot unchanged. */
+int stratego_reset(stratego_ctx* ctx, const int32_t* slots_dev, int32_t n, const void* states_dev);
+
+/* Legal-action mask of the acting player of every game (App. B
+ * ComputeLegalActionMask; App. A movement rules).  mask_dev: uint64[N][157].
+ * num_legal_dev: int16[N] or NULL.  Finished games get an all-zero mask. */
+int stratego_legal_mask(stratego_ctx* ctx, uint64_t* mask_dev, int16_t* num_legal_dev);
+
+/* One uniformly random legal action per game (App. B SampleRandomLegalAction):
+ * the r-th set bit of the mask in ascending action order, with
+ * r = (u * n) >> 32, u = word x of Philox4x32-10(key = seed,
+ * counter = (game id, ply, episode, 0)), n = num_legal.  -1 when n == 0. */
+int stratego_sample_actions(stratego_ctx* ctx, const uint64_t* mask_dev,
+                            const int16_t* num_legal_dev, int16_t* actions_dev);
+
+/* Apply one action per game (App. B ApplyActions; App. A battles; App. C.1
+ * history features).  actions_dev: int16[N]; -1 = no-op.  Outputs (each
+ * int8/uint8/int16 [N], any may be NULL): done = 1 if the game is terminal
+ * after this call (with auto-reset: it ended in this call and was restarted),
+ * outcome (+1 red won, -1 blue won, 0 draw), reason (1 flag captured, 2 forced
+ * win, 3 forced draw, 4 k-move rule, 5 maximum length), ep_len = moves in the
+ * finished episode; all zero for games that are not done.  An illegal action
+ * for a live game leaves that game unchanged and latches
+ * E_ILLEGAL_ACTION with the lowest such slot. */
+int stratego_step(stratego_ctx* ctx, const int16_t* actions_dev, int8_t* done_dev,
+                  int8_t* outcome_dev, uint8_t* reason_dev, int16_t* ep_len_dev);
+
+/* Information states of both players (App. C): obs_dev uint8[N][2][488][10][10]. */
+int stratego_encode_obs(stratego_ctx* ctx, uint8_t* obs_dev);
+
+/* Copy the N canonical records (1536 bytes each) to states_dev (device). */
+int stratego_export_states(stratego_ctx* ctx, void* states_dev);
+
+/* Fused engine (one persistent kernel per ply): for each of nplies plies and
+ * every game, legal mask -> uniform sample -> encode both players' obs of the
+ * pre-move state -> step (with the context's auto-reset).  The per-ply
+ * outputs mask_dev, num_legal_dev and obs_dev are overwritten each ply (they
+ * hold the last ply's values); actions/done/outcome/reason/ep_len are written
+ * per ply as [nplies][N] arrays.  Any output may be NULL (obs_dev NULL skips
+ * the encoding).  With use_graph = 1 the nplies launches are captured once
+ * into a hipGraph (per distinct argument set) and replayed.  ply_ns_dev, if
+ * not NULL, receives int64[nplies] per-ply device durations in nanoseconds
+ * (first wave start to last wave end). */
+int stratego_run_plies(stratego_ctx* ctx, int32_t nplies, uint64_t* mask_dev,
+                       int16_t* num_legal_dev, int16_t* actions_dev, uint8_t* obs_dev,
+                       int8_t* done_dev, int8_t* outcome_dev, uint8_t* reason_dev,
+                       int16_t* ep_len_dev, int32_t use_graph, int64_t* ply_ns_dev);
+
+/* Same as stratego_run_plies over a subset of slots (serving): slots_dev
+ * int32[nslots] (distinct, each in [0, N); an out-of-range entry is skipped
+ * and latches E_BAD_STATE with its list position); per-game outputs are
+ * indexed by position in the slot list ([nplies][nslots], obs
+ * [nslots][2][488][100]).  No graph. */
+int stratego_run_plies_slots(stratego_ctx* ctx, const int32_t* slots_dev, int32_t nslots,
+                             int32_t nplies, uint64_t* mask_dev, int16_t* actions_dev,
+                             uint8_t* obs_dev, int8_t* done_dev, int8_t* outcome_dev,
+                             uint8_t* reason_dev, int16_t* ep_len_dev);
+
+/* Search support (paper section 2.5, App. B reset to non-initial states):
+ * slot i*per + j (i < nsrc, j < per) receives src record i with the hidden
+ * types of the player not to move redrawn uniformly among assignments
+ * consistent with public information (revealed and dead pieces keep their
+ * types; a piece that has moved is neither Flag nor Bomb), drawn from
+ * Philox4x32-10(key = seed, counter = (new id, block, episode, 3)); the new
+ * game id is game_id_base + i*per + j.  nsrc*per must not exceed N. */
+int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int32_t nsrc,
+                             int32_t per, uint32_t game_id_base);
+
+/* Time the fused engine for every (games_per_wg, lds_segments) pair that fits
+ * the device, plies plies each, restoring the game states afterwards, and
+ * adopt the fastest.  report (may be NULL) receives up to max_entries rows of
+ * {games_per_wg, lds_segments, microseconds per ply}; returns the number of
+ * rows through n_entries.  Synchronises the stream. */
+typedef struct {
+  int32_t games_per_wg;
+  int32_t lds_segments;
+  double us_per_ply;
+} stratego_tune_entry;
+int stratego_autotune(stratego_ctx* ctx, uint8_t* obs_dev, uint64_t* mask_dev, int32_t plies,
+                      stratego_tune_entry* report, int32_t max_entries, int32_t* n_entries);
+
+/* Current fused-engine tiling. */
+int stratego_get_tiling(stratego_ctx* ctx, int32_t* games_per_wg, int32_t* lds_segments);
+int stratego_set_tiling(stratego_ctx* ctx, int32_t games_per_wg, int32_t lds_segments);
+
+/* Synchronise the stream, then report and clear the latched device error:
+ * returns STRATEGO_OK, E_ILLEGAL_ACTION or E_BAD_STATE; first_bad_slot (may
+ * be NULL) receives the lowest offending slot or -1. */
+int stratego_get_error(stratego_ctx* ctx, int32_t* first_bad_slot);
+
+/* Number of state updates (game steps) applied by step/run_plies so far
+ * (App. B CurrentStep). */
+int stratego_current_step(stratego_ctx* ctx, int64_t* steps);
+
+/* Synchronise and free everything the context owns. */
+int stratego_destroy(stratego_ctx* ctx);
+
+/* Static description of an error code. */
+const char* stratego_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STRATEGO_H */

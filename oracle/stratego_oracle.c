@@ -421,7 +421,8 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
     /* 2. evasion: the mover was threatened by A on the previous move and now
      *    moves to an empty square that is not adjacent to A */
     int target = st->board[to];
-    if (A >= 0 && adjacent(from, a) && target == EMPTY && !adjacent(to, a))
+    if (A >= 0 && adjacent(from, a) && target == EMPTY && !adjacent(to, a) &&
+        !(st->piece[A].revealed && !is_movable_type(st->piece[A].type)))
         st->piece[X].evade |= 1u << hidden_or_type10(&st->piece[A]);
 
     /* 3. resolve the move or battle */

@@ -1,0 +1,972 @@
+// Device-side Stratego engine for gfx950: one wavefront (64 lanes) owns one
+// game at a time.  The game's canonical record is staged in LDS; square-wise
+// work maps lane l to squares l and l+64, piece-wise work to ids l and l+64,
+// and scalar rule logic runs on lane 0 with wave-level fences in between.
+//
+// Paper: arXiv 2511.07312.  App. A (rules, Table "pieces"), App. B
+// (simulator: ApplyActions, auto-reset, reset to non-initial states,
+// SampleRandomLegalAction), App. C (information state), App. D.1 (k-move rule,
+// maximum game length).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSquares = 100;
+constexpr int kPieces = 80;
+constexpr int kChannels = 488;
+constexpr int kObsPerObserver = kChannels * 100;  // 48800
+constexpr int kObsPerGame = 2 * kObsPerObserver;  // 97600
+constexpr int kMaskWords = 157;
+constexpr int kRecordBytes = 1536;
+
+// canonical record offsets
+constexpr int kOffGameId = 0;
+constexpr int kOffEpisode = 4;
+constexpr int kOffPly = 8;
+constexpr int kOffBattleless = 12;
+constexpr int kOffRingCount = 16;
+constexpr int kOffDone = 17;
+constexpr int kOffOutcome = 18;
+constexpr int kOffReason = 19;
+constexpr int kOffRedraws = 20;
+constexpr int kOffBoard = 64;
+constexpr int kOffRing = 164;
+constexpr int kOffPieces = 256;
+
+constexpr int kEmpty = -1;
+constexpr int kLake = -2;
+
+// piece types in the channel order of App. C.1 (channels 0-11)
+constexpr int kSpy = 0, kScout = 1, kMiner = 2, kMarshal = 9, kFlag = 10, kBomb = 11;
+
+// per-wave LDS slab
+constexpr int kSlabProbQ = 1536;    // uint8 [owner][moved][type] quantised probabilities
+constexpr int kSlabCounts = 1600;   // int32 [28]: known[2][12], hidden[2], moved_hidden[2]
+constexpr int kSlabScratch = 1712;  // uint8 [80]: setup / resample work arrays
+constexpr int kSlabImage = 1792;    // obs image segment (also holds the to-square sets)
+
+__host__ __device__ constexpr int seg_channels_for(int segments) {
+  return segments == 1 ? 488 : segments == 2 ? 244 : segments == 4 ? 124 : 64;
+}
+__host__ __device__ constexpr int slab_bytes_for(int segments) {
+  return kSlabImage + 100 * seg_channels_for(segments);
+}
+
+enum : int { kReasonNone = 0, kReasonFlag = 1, kReasonForcedWin = 2, kReasonForcedDraw = 3,
+             kReasonKMove = 4, kReasonMaxMoves = 5 };
+
+struct Rules {
+  uint64_t seed;
+  int32_t k_battleless;
+  int32_t max_moves;
+  int32_t auto_reset;
+};
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Order LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------- record access
+__device__ __forceinline__ int board_at(const uint8_t* R, int s) { return (int8_t)R[kOffBoard + s]; }
+__device__ __forceinline__ void set_board(uint8_t* R, int s, int v) { R[kOffBoard + s] = (uint8_t)(int8_t)v; }
+__device__ __forceinline__ uint32_t* piece_words(uint8_t* R, int id) {
+  return reinterpret_cast<uint32_t*>(R + kOffPieces + 16 * id);
+}
+__device__ __forceinline__ const uint32_t* piece_words(const uint8_t* R, int id) {
+  return reinterpret_cast<const uint32_t*>(R + kOffPieces + 16 * id);
+}
+__device__ __forceinline__ uint32_t hdr_u32(const uint8_t* R, int off) {
+  return *reinterpret_cast<const uint32_t*>(R + off);
+}
+__device__ __forceinline__ void set_hdr_u32(uint8_t* R, int off, uint32_t v) {
+  *reinterpret_cast<uint32_t*>(R + off) = v;
+}
+
+// w0 fields: type 0-3, alive 4, revealed 5, moved 6, death cause 7-9,
+// death square 10-16, been-protected-against 17-29
+__device__ __forceinline__ int p_type(uint32_t w0) { return w0 & 15; }
+__device__ __forceinline__ bool p_alive(uint32_t w0) { return (w0 >> 4) & 1; }
+__device__ __forceinline__ bool p_revealed(uint32_t w0) { return (w0 >> 5) & 1; }
+__device__ __forceinline__ bool p_moved(uint32_t w0) { return (w0 >> 6) & 1; }
+__device__ __forceinline__ int owner(int id) { return id >= 40 ? 1 : 0; }
+__device__ __forceinline__ int start_sq(int id) { return id < 40 ? id : 139 - id; }
+__device__ __forceinline__ bool movable_type(int t) { return t < kFlag; }
+
+// threat / evasion / adjacency slot of a target piece: revealed Spy..Marshal
+// -> its type, hidden -> 10; revealed Flag/Bomb -> -1 (no channel)
+__device__ __forceinline__ int slot10(uint32_t w0) {
+  if (!p_revealed(w0)) return 10;
+  int t = p_type(w0);
+  return t < kFlag ? t : -1;
+}
+// protection slot: revealed Spy..Marshal -> type, revealed Bomb -> 10, hidden -> 12
+__device__ __forceinline__ int slot13(uint32_t w0) {
+  if (!p_revealed(w0)) return 12;
+  int t = p_type(w0);
+  return t == kBomb ? 10 : t;
+}
+
+__device__ __forceinline__ bool adjacent(int a, int b) {
+  int ra = a / 10, ca = a - 10 * ra, rb = b / 10, cb = b - 10 * rb;
+  int d = abs(ra - rb) + abs(ca - cb);
+  return d == 1;
+}
+
+// orthogonal on-board neighbour k (0 up, 1 down, 2 left, 3 right) or -1
+__device__ __forceinline__ int neighbour(int s, int k) {
+  int r = s / 10, c = s - 10 * r;
+  switch (k) {
+    case 0: return r < 9 ? s + 10 : -1;
+    case 1: return r > 0 ? s - 10 : -1;
+    case 2: return c > 0 ? s - 1 : -1;
+    default: return c < 9 ? s + 1 : -1;
+  }
+}
+
+__device__ __forceinline__ bool is_lake_sq(int s) {
+  int r = s / 10, c = s - 10 * r;
+  return (r == 4 || r == 5) && (c == 2 || c == 3 || c == 6 || c == 7);
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32
+// multiplies with a Weyl key schedule.
+__device__ __forceinline__ uint4 philox(uint4 c, uint64_t seed) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint32_t mulshift(uint32_t u, uint32_t n) {
+  return (uint32_t)(((uint64_t)u * n) >> 32);
+}
+
+// sequential words x, y, z, w of blocks 0, 1, ... of one counter stream
+struct WordStream {
+  uint64_t seed;
+  uint32_t id, episode, tag, block;
+  uint4 buf;
+  int used;
+  __device__ void init(uint64_t s, uint32_t gid, uint32_t ep, uint32_t t) {
+    seed = s; id = gid; episode = ep; tag = t; block = 0; used = 4;
+  }
+  __device__ uint32_t next() {
+    if (used == 4) {
+      buf = philox(make_uint4(id, block, episode, tag), seed);
+      ++block;
+      used = 0;
+    }
+    uint32_t v = used == 0 ? buf.x : used == 1 ? buf.y : used == 2 ? buf.z : buf.w;
+    ++used;
+    return v;
+  }
+};
+
+// ---------------------------------------------------------------- global <-> LDS
+__device__ __forceinline__ void load_record(uint8_t* R, const uint8_t* g) {
+  const int lane = lane_id();
+  const uint4* src = reinterpret_cast<const uint4*>(g);
+  uint4* dst = reinterpret_cast<uint4*>(R);
+  dst[lane] = src[lane];
+  if (lane < 32) dst[64 + lane] = src[64 + lane];
+  wave_sync();
+}
+
+__device__ __forceinline__ void store_record(uint8_t* g, const uint8_t* R) {
+  const int lane = lane_id();
+  const uint4* src = reinterpret_cast<const uint4*>(R);
+  uint4* dst = reinterpret_cast<uint4*>(g);
+  dst[lane] = src[lane];
+  if (lane < 32) dst[64 + lane] = src[64 + lane];
+}
+
+// ---------------------------------------------------------------- legal moves
+// Destinations of the piece on square x for player p as a 100-bit set (App. A:
+// one orthogonal step to an empty or enemy square; Scouts any distance over
+// empty squares, possibly ending on an enemy; no jumping over lakes or pieces;
+// Flag and Bomb never move).
+__device__ __forceinline__ void destinations(const uint8_t* R, int x, int p, uint64_t& lo,
+                                             uint64_t& hi) {
+  lo = 0;
+  hi = 0;
+  int id = board_at(R, x);
+  if (id < 0 || owner(id) != p) return;
+  int t = p_type(piece_words(R, id)[0]);
+  if (!movable_type(t)) return;
+  const int r = x / 10, c = x - 10 * r;
+  const int reach = t == kScout ? 9 : 1;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int delta = d == 0 ? 10 : d == 1 ? -10 : d == 2 ? -1 : 1;
+    const int room = d == 0 ? 9 - r : d == 1 ? r : d == 2 ? c : 9 - c;
+    const int steps = room < reach ? room : reach;
+    int y = x;
+    for (int k = 0; k < steps; ++k) {
+      y += delta;
+      int o = board_at(R, y);
+      if (o == kLake) break;
+      bool enemy = o >= 0 && owner(o) != p;
+      if (o == kEmpty || enemy) {
+        if (y < 64) lo |= 1ull << y;
+        else hi |= 1ull << (y - 64);
+      }
+      if (o != kEmpty) break;
+    }
+  }
+}
+
+// True when player p owns a movable piece with an adjacent empty or enemy
+// square, i.e. p has at least one legal move.
+__device__ __forceinline__ bool has_move(const uint8_t* R, int p) {
+  const int lane = lane_id();
+  bool any = false;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int x = lane + 64 * h;
+    if (x >= kSquares) break;
+    int id = board_at(R, x);
+    if (id < 0 || owner(id) != p || !movable_type(p_type(piece_words(R, id)[0]))) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int y = neighbour(x, k);
+      if (y < 0) continue;
+      int o = board_at(R, y);
+      if (o == kEmpty || (o >= 0 && owner(o) != p)) any = true;
+    }
+  }
+  return ballot(any) != 0;
+}
+
+// Direct test of one action against the movement rule (used to validate
+// caller-supplied actions).
+__device__ __forceinline__ bool action_is_legal(const uint8_t* R, int p, int action) {
+  if (action < 0 || action >= 10000) return false;
+  int from = action / 100, to = action - 100 * from;
+  if (from == to) return false;
+  int id = board_at(R, from);
+  if (id < 0 || owner(id) != p) return false;
+  int t = p_type(piece_words(R, id)[0]);
+  if (!movable_type(t)) return false;
+  int tgt = board_at(R, to);
+  if (tgt == kLake || (tgt >= 0 && owner(tgt) == p)) return false;
+  int rf = from / 10, cf = from - 10 * rf, rt = to / 10, ct = to - 10 * rt;
+  if (rf != rt && cf != ct) return false;
+  int dist = abs(rf - rt) + abs(cf - ct);
+  if (t != kScout && dist != 1) return false;
+  int stp = rf == rt ? (ct > cf ? 1 : -1) : (rt > rf ? 10 : -10);
+  for (int y = from + stp; y != to; y += stp)
+    if (board_at(R, y) != kEmpty) return false;
+  return true;
+}
+
+// Mask words of the acting player: lane l returns words l, 64+l, 128+l (the
+// last only for l < 29).  ts is the LDS array of 100 destination sets
+// (2 x u64 each).  Returns the number of legal actions (wave-uniform).
+__device__ __forceinline__ int legal_mask_words(const uint8_t* R, uint64_t* ts, uint64_t w[3]) {
+  const int lane = lane_id();
+  const int p = hdr_u32(R, kOffPly) & 1;
+  const bool done = R[kOffDone] != 0;
+  int cnt = 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int x = lane + 64 * h;
+    if (x < kSquares) {
+      uint64_t lo, hi;
+      if (done) { lo = 0; hi = 0; }
+      else destinations(R, x, p, lo, hi);
+      ts[2 * x] = lo;
+      ts[2 * x + 1] = hi;
+      cnt += __popcll(lo) + __popcll(hi);
+    }
+  }
+  if (lane == 0) { ts[200] = 0; ts[201] = 0; }   // sentinel set after square 99
+  wave_sync();
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    int word = lane + 64 * g;
+    uint64_t v = 0;
+    if (word < kMaskWords) {
+      int a0 = 64 * word;
+      int f0 = a0 / 100;
+      int off = a0 - 100 * f0;
+      uint64_t lo = ts[2 * f0], hi = ts[2 * f0 + 1];
+      v = off == 0 ? lo : off < 64 ? (lo >> off) | (hi << (64 - off)) : hi >> (off - 64);
+      int rem = 100 - off;   // bits of set f0 that landed in this word
+      if (rem < 64) v |= ts[2 * (f0 + 1)] << rem;
+    }
+    w[g] = v;
+  }
+  return wave_sum(cnt);
+}
+
+// k-th (0-based) set bit of a 64-bit word
+__device__ __forceinline__ int select_bit(uint64_t w, int k) {
+  int pos = 0;
+  uint32_t v = (uint32_t)w;
+  int c = __popc(v);
+  if (k >= c) { k -= c; pos = 32; v = (uint32_t)(w >> 32); }
+  c = __popc(v & 0xFFFFu);
+  if (k >= c) { k -= c; pos += 16; v >>= 16; }
+  c = __popc(v & 0xFFu);
+  if (k >= c) { k -= c; pos += 8; v >>= 8; }
+  c = __popc(v & 0xFu);
+  if (k >= c) { k -= c; pos += 4; v >>= 4; }
+  c = __popc(v & 0x3u);
+  if (k >= c) { k -= c; pos += 2; v >>= 2; }
+  c = v & 1u;
+  if (k >= c) pos += 1;
+  return pos;
+}
+
+// Uniform legal action from mask words held as in legal_mask_words.
+__device__ __forceinline__ int sample_from_words(const uint64_t w[3], int n, uint64_t seed,
+                                                 uint32_t game_id, uint32_t ply, uint32_t episode) {
+  if (n <= 0) return -1;
+  uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  int r = (int)mulshift(u.x, (uint32_t)n);
+  int base = 0;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    int c = __popcll(w[g]);
+    int incl = wave_incl_scan(c);
+    int total = __shfl(incl, 63, 64);
+    if (r < base + total) {
+      uint64_t hit = ballot(base + incl > r);
+      int L = __ffsll((unsigned long long)hit) - 1;
+      int excl = __shfl(incl - c, L, 64);
+      uint64_t word = __shfl(w[g], L, 64);
+      int bit = select_bit(word, r - base - excl);
+      return 64 * (64 * g + L) + bit;
+    }
+    base += total;
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------- terminal check
+// App. A: capture of the flag wins; a player to move without legal moves loses,
+// a draw when neither side can move; App. D.1: k-move rule, maximum length.
+// Priority: flag > no moves > k-move > max moves.  Writes done/outcome/reason.
+__device__ __forceinline__ void terminal_check(uint8_t* R, const Rules& rules, int flag_winner) {
+  const int ply = (int)hdr_u32(R, kOffPly);
+  const int q = ply & 1;
+  int done = 0, outcome = 0, reason = kReasonNone;
+  if (flag_winner >= 0) {
+    done = 1; outcome = flag_winner == 0 ? 1 : -1; reason = kReasonFlag;
+  } else if (!has_move(R, q)) {
+    done = 1;
+    if (!has_move(R, 1 - q)) { outcome = 0; reason = kReasonForcedDraw; }
+    else { outcome = (1 - q) == 0 ? 1 : -1; reason = kReasonForcedWin; }
+  } else if ((int)hdr_u32(R, kOffBattleless) >= rules.k_battleless) {
+    done = 1; reason = kReasonKMove;
+  } else if (ply >= rules.max_moves) {
+    done = 1; reason = kReasonMaxMoves;
+  }
+  if (lane_id() == 0) {
+    R[kOffDone] = (uint8_t)done;
+    R[kOffOutcome] = (uint8_t)(int8_t)outcome;
+    R[kOffReason] = (uint8_t)reason;
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------- setup / reset
+// type of the i-th element of the sorted initial multiset (Table "pieces":
+// 1 Spy, 8 Scouts, 5 Miners, 4 Sergeants, 4 Lieutenants, 4 Captains, 3 Majors,
+// 2 Colonels, 1 General, 1 Marshal, 1 Flag, 6 Bombs)
+__device__ __forceinline__ int multiset_type(int i) {
+  return i < 1 ? 0 : i < 9 ? 1 : i < 14 ? 2 : i < 18 ? 3 : i < 22 ? 4 : i < 26 ? 5
+       : i < 29 ? 6 : i < 31 ? 7 : i < 32 ? 8 : i < 33 ? 9 : i < 34 ? 10 : 11;
+}
+
+__device__ __forceinline__ int initial_count(int t) {
+  return t == 0 ? 1 : t == 1 ? 8 : t == 2 ? 5 : t <= 5 ? 4 : t == 6 ? 3 : t == 7 ? 2 : t <= 10 ? 1 : 6;
+}
+
+// Fresh uniformly random setup of both players for (game id, episode): a
+// Durstenfeld shuffle of the multiset per player, red id i on square i, blue
+// id 40+i on square 99-i.
+__device__ void fresh_setup(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_t game_id,
+                            uint32_t episode, uint32_t redraws) {
+  const int lane = lane_id();
+  uint4* r4 = reinterpret_cast<uint4*>(R);
+  r4[lane] = make_uint4(0, 0, 0, 0);
+  if (lane < 32) r4[64 + lane] = make_uint4(0, 0, 0, 0);
+  wave_sync();
+  if (lane < 2) {
+    uint8_t* a = scratch + 40 * lane;
+    for (int i = 0; i < 40; ++i) a[i] = (uint8_t)multiset_type(i);
+    WordStream ws;
+    ws.init(seed, game_id, episode, 1u + (uint32_t)lane);
+    for (int i = 39; i >= 1; --i) {
+      int j = (int)mulshift(ws.next(), (uint32_t)(i + 1));
+      uint8_t tmp = a[i];
+      a[i] = a[j];
+      a[j] = tmp;
+    }
+  }
+  if (lane == 0) {
+    set_hdr_u32(R, kOffGameId, game_id);
+    set_hdr_u32(R, kOffEpisode, episode);
+    set_hdr_u32(R, kOffRedraws, redraws);
+  }
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int s = lane + 64 * h;
+    if (s < kSquares) {
+      int v = kEmpty;
+      if (is_lake_sq(s)) v = kLake;
+      else if (s < 40) v = s;
+      else if (s >= 60) v = 139 - s;
+      set_board(R, s, v);
+    }
+    int id = lane + 64 * h;
+    if (id < kPieces) {
+      int t = scratch[id];   // id < 40: red slot id; id >= 40: blue slot id-40
+      piece_words(R, id)[0] = (uint32_t)t | (1u << 4) | (127u << 10);
+    }
+  }
+  wave_sync();
+}
+
+__device__ void reset_game(uint8_t* R, uint8_t* scratch, const Rules& rules, uint32_t game_id,
+                           uint32_t episode, uint32_t redraws) {
+  fresh_setup(R, scratch, rules.seed, game_id, episode, redraws);
+  terminal_check(R, rules, -1);
+  // A setup that is already terminal is replaced by the next episode's setup
+  // (probability ~4e-6 per game); the bound only guards against a hang.
+  int guard = 0;
+  while (R[kOffDone] && rules.auto_reset && guard < 1000) {
+    ++episode;
+    ++redraws;
+    ++guard;
+    fresh_setup(R, scratch, rules.seed, game_id, episode, redraws);
+    terminal_check(R, rules, -1);
+  }
+}
+
+// ---------------------------------------------------------------- move application
+// Applies a legal action of the player to move and updates the history
+// features of App. C.1: active adjacency (attacks available but not taken,
+// before the move), evasion (a piece threatened by the previous move steps
+// to an empty square away from the threatener), battle resolution with
+// reveal and death records, threats made by the mover, and protection (a
+// non-battle reply to a threat in which the mover newly becomes adjacent to a
+// square next to the threatener).  Then pushes the move into the ring,
+// advances the counters and runs the terminal check.
+__device__ void apply_action(uint8_t* R, const Rules& rules, int action) {
+  const int lane = lane_id();
+  const int from = action / 100, to = action - 100 * (action / 100);
+  const int ply = (int)hdr_u32(R, kOffPly);
+  const int p = ply & 1, q = 1 - p;
+  const int X = board_at(R, from);
+
+  // previous move: its mover A (still standing on its destination a)
+  int A = -1, a = -1;
+  bool prev_threat = false;
+  const int ring_count = R[kOffRingCount];
+  if (ring_count > 0) {
+    int slot = (ply - 1) & 31;
+    int pt = R[kOffRing + 2 * slot + 1];
+    int id = board_at(R, pt);
+    if (id >= 0 && owner(id) == q) {
+      A = id;
+      a = pt;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int y = neighbour(a, k);
+        if (y < 0) continue;
+        int o = board_at(R, y);
+        if (o >= 0 && owner(o) == p) prev_threat = true;
+      }
+    }
+  }
+
+  // 1. active adjacency (pre-move), lane-parallel over squares
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int x = lane + 64 * h;
+    if (x >= kSquares) break;
+    int id = board_at(R, x);
+    if (id < 0 || owner(id) != p) continue;
+    if (!movable_type(p_type(piece_words(R, id)[0]))) continue;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int y = neighbour(x, k);
+      if (y < 0) continue;
+      int e = board_at(R, y);
+      if (e < 0 || owner(e) != q) continue;
+      if (x == from && y == to) continue;
+      int sl = slot10(piece_words(R, e)[0]);
+      if (sl >= 0) bits |= 1u << sl;
+    }
+    if (bits) piece_words(R, id)[2] |= bits;
+  }
+  wave_sync();
+
+  int flag_winner = -1;
+  if (lane == 0) {
+    uint32_t* px = piece_words(R, X);
+    const int tgt = board_at(R, to);
+    // 2. evasion
+    if (A >= 0 && adjacent(from, a) && tgt == kEmpty && !adjacent(to, a)) {
+      const int sl = slot10(piece_words(R, A)[0]);
+      if (sl >= 0) px[1] |= (1u << sl) << 11;
+    }
+    // 3-4. move or battle with death records
+    const bool battle = tgt >= 0;
+    bool attacker_alive = true;
+    if (!battle) {
+      set_board(R, to, X);
+      set_board(R, from, kEmpty);
+    } else {
+      uint32_t* py = piece_words(R, tgt);
+      const int ta = p_type(px[0]), td = p_type(py[0]);
+      const bool rY = p_revealed(py[0]);
+      int res;   // 0 attacker wins, 1 defender wins, 2 tie (Table "pieces")
+      if (td == kFlag) res = 0;
+      else if (td == kBomb) res = ta == kMiner ? 0 : 1;
+      else if (ta == kSpy && td == kMarshal) res = 0;
+      else res = ta > td ? 0 : ta < td ? 1 : 2;
+      px[0] |= 1u << 5;
+      py[0] |= 1u << 5;
+      if (td == kFlag) flag_winner = p;
+      set_board(R, from, kEmpty);
+      const uint32_t clear = (1u << 4) | (7u << 7) | (127u << 10);
+      if (res == 0) {
+        set_board(R, to, X);
+        py[0] = (py[0] & ~clear) | ((rY ? 4u : 6u) << 7) | ((uint32_t)to << 10);
+      } else if (res == 1) {
+        attacker_alive = false;
+        px[0] = (px[0] & ~clear) | ((rY ? 1u : 3u) << 7) | ((uint32_t)to << 10);
+      } else {
+        attacker_alive = false;
+        set_board(R, to, kEmpty);
+        px[0] = (px[0] & ~clear) | ((rY ? 2u : 3u) << 7) | ((uint32_t)to << 10);
+        py[0] = (py[0] & ~clear) | ((rY ? 5u : 6u) << 7) | ((uint32_t)to << 10);
+      }
+    }
+    px[0] |= 1u << 6;   // moved
+    // 5. threats by the mover from its destination
+    if (attacker_alive) {
+      for (int k = 0; k < 4; ++k) {
+        int y = neighbour(to, k);
+        if (y < 0) continue;
+        int e = board_at(R, y);
+        if (e < 0 || owner(e) != q) continue;
+        int sl = slot10(piece_words(R, e)[0]);
+        if (sl >= 0) px[1] |= 1u << sl;
+      }
+    }
+    // 6. protection
+    if (!battle && A >= 0 && prev_threat) {
+      const uint32_t wA = piece_words(R, A)[0];
+      const uint32_t bitA = 1u << slot13(wA);
+      for (int k = 0; k < 4; ++k) {
+        int s = neighbour(a, k);
+        if (s < 0 || is_lake_sq(s)) continue;
+        if (!adjacent(s, to) || s == from || adjacent(s, from)) continue;
+        int o = board_at(R, s);
+        if (o >= 0 && owner(o) == p) {
+          uint32_t* pb = piece_words(R, o);
+          px[2] |= (1u << slot13(pb[0])) << 11;
+          px[3] |= bitA;
+          pb[3] |= (1u << slot13(px[0])) << 13;
+          pb[0] |= bitA << 17;
+        } else if (o == kEmpty) {
+          px[2] |= (1u << 11) << 11;
+          px[3] |= bitA;
+        }
+      }
+    }
+    // 7-8. ring and counters
+    const int slot = ply & 31;
+    R[kOffRing + 2 * slot] = (uint8_t)from;
+    R[kOffRing + 2 * slot + 1] = (uint8_t)to;
+    if (ring_count < 32) R[kOffRingCount] = (uint8_t)(ring_count + 1);
+    set_hdr_u32(R, kOffPly, (uint32_t)(ply + 1));
+    set_hdr_u32(R, kOffBattleless, battle ? 0u : hdr_u32(R, kOffBattleless) + 1u);
+  }
+  flag_winner = __shfl(flag_winner, 0, 64);
+  wave_sync();
+  terminal_check(R, rules, flag_winner);
+}
+
+struct StepOut {
+  int done, outcome, reason, ep_len;
+  bool illegal;
+};
+
+// One ApplyActions step of one game (App. B).  Returns the per-game outputs.
+__device__ StepOut step_game(uint8_t* R, uint8_t* scratch, const Rules& rules, int action) {
+  StepOut o{0, 0, 0, 0, false};
+  if (R[kOffDone]) {
+    o.done = 1;
+    o.outcome = (int8_t)R[kOffOutcome];
+    o.reason = R[kOffReason];
+    o.ep_len = (int)hdr_u32(R, kOffPly);
+    if (rules.auto_reset)
+      reset_game(R, scratch, rules, hdr_u32(R, kOffGameId), hdr_u32(R, kOffEpisode) + 1,
+                 hdr_u32(R, kOffRedraws));
+    return o;
+  }
+  if (action == -1) return o;
+  const int p = hdr_u32(R, kOffPly) & 1;
+  if (!action_is_legal(R, p, action)) {
+    o.illegal = true;
+    return o;
+  }
+  apply_action(R, rules, action);
+  if (R[kOffDone]) {
+    o.done = 1;
+    o.outcome = (int8_t)R[kOffOutcome];
+    o.reason = R[kOffReason];
+    o.ep_len = (int)hdr_u32(R, kOffPly);
+    if (rules.auto_reset)
+      reset_game(R, scratch, rules, hdr_u32(R, kOffGameId), hdr_u32(R, kOffEpisode) + 1,
+                 hdr_u32(R, kOffRedraws));
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------- probabilities
+// Channels 12-35 (App. C.1): chance that a hidden piece has type T when the
+// hidden types are a uniform assignment of the owner's remaining multiset in
+// which no moved piece is a Flag or Bomb.  With H hidden pieces, I hidden
+// Flag+Bomb, M moved hidden, U = H - M unmoved hidden and n_T remaining of T:
+// moved: n_T/(H-I) for movable T, 0 otherwise; unmoved: n_T/U for Flag/Bomb,
+// n_T(U-I)/(U(H-I)) for movable T.  Stored as round-half-up(255 p) in
+// probq[owner][moved][type].
+__device__ __forceinline__ uint32_t quant255(uint32_t num, uint32_t den) {
+  return den == 0 ? 0u : (510u * num + den) / (2u * den);
+}
+
+__device__ void compute_probq(const uint8_t* R, uint8_t* slab) {
+  const int lane = lane_id();
+  int* cnt = reinterpret_cast<int*>(slab + kSlabCounts);   // known[2][12], H[2], M[2]
+  if (lane < 28) cnt[lane] = 0;
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int id = lane + 64 * h;
+    if (id < kPieces) {
+      uint32_t w0 = piece_words(R, id)[0];
+      int w = owner(id);
+      if (!p_alive(w0) || p_revealed(w0)) {
+        atomicAdd(&cnt[12 * w + p_type(w0)], 1);
+      } else {
+        atomicAdd(&cnt[24 + w], 1);
+        if (p_moved(w0)) atomicAdd(&cnt[26 + w], 1);
+      }
+    }
+  }
+  wave_sync();
+  if (lane < 48) {
+    const int w = lane / 24, m = (lane / 12) & 1, t = lane % 12;
+    const int n_t = initial_count(t) - cnt[12 * w + t];
+    const int H = cnt[24 + w], M = cnt[26 + w], U = H - M;
+    const int I = (initial_count(kFlag) - cnt[12 * w + kFlag]) + (initial_count(kBomb) - cnt[12 * w + kBomb]);
+    uint32_t v;
+    if (m) v = movable_type(t) ? quant255((uint32_t)n_t, (uint32_t)(H - I)) : 0u;
+    else if (!movable_type(t)) v = quant255((uint32_t)n_t, (uint32_t)U);
+    else v = quant255((uint32_t)(n_t * (U - I)), (uint32_t)(U * (H - I)));
+    slab[kSlabProbQ + lane] = (uint8_t)v;
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------- encoding
+// Writes byte v at (channel c, frame square f) of the current image segment
+// when c lies in [c_lo, c_hi).
+struct SegWriter {
+  uint8_t* img;
+  int c_lo, c_hi;
+  __device__ __forceinline__ void put(int c, int f, uint8_t v) const {
+    if (c >= c_lo && c < c_hi) img[(c - c_lo) * 100 + f] = v;
+  }
+  __device__ __forceinline__ bool overlaps(int a, int b) const { return a < c_hi && b > c_lo; }
+};
+
+// Scatter the non-zero bytes of observer o's channels [c_lo, c_hi) into the
+// zeroed image segment (App. C.1 channel table and App. C.2 move planes).
+__device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rules& rules, int o,
+                                const SegWriter& W) {
+  const int lane = lane_id();
+  const int ply = (int)hdr_u32(R, kOffPly);
+  // squares
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    int s = lane + 64 * h;
+    if (s >= kSquares) break;
+    const int f = o == 0 ? s : 99 - s;
+    if (W.overlaps(41, 43)) {
+      W.put(41, f, (uint8_t)quant255((uint32_t)ply, (uint32_t)rules.max_moves));
+      W.put(42, f, (uint8_t)quant255(hdr_u32(R, kOffBattleless), (uint32_t)rules.k_battleless));
+    }
+    const int id = board_at(R, s);
+    if (id == kLake) continue;
+    if (id == kEmpty) {
+      W.put(38, f, 1);
+      continue;
+    }
+    const uint32_t* pw = piece_words(R, id);
+    const uint32_t w0 = pw[0];
+    const int t = p_type(w0);
+    const bool own = owner(id) == o;
+    const bool rev = p_revealed(w0), mv = p_moved(w0);
+    if (W.overlaps(0, 41)) {
+      if (own) {
+        W.put(t, f, 1);
+        if (!rev) W.put(36, f, 1);
+        if (mv) W.put(39, f, 1);
+      } else {
+        if (!rev) W.put(37, f, 1);
+        if (mv) W.put(40, f, 1);
+      }
+      const int pbase = own ? 24 : 12;
+      if (rev) {
+        W.put(pbase + t, f, 255);
+      } else {
+        const uint8_t* pq = slab + kSlabProbQ + 24 * owner(id) + 12 * (mv ? 1 : 0);
+        for (int k = 0; k < 12; ++k)
+          if (pq[k]) W.put(pbase + k, f, pq[k]);
+      }
+    }
+    const int hbase = own ? 43 : 76;
+    if (W.overlaps(hbase, hbase + 33)) {
+      uint32_t th = pw[1] & 0x7FFu, ev = (pw[1] >> 11) & 0x7FFu, ad = pw[2] & 0x7FFu;
+      while (th) { int j = __ffs(th) - 1; th &= th - 1; W.put(hbase + j, f, 1); }
+      while (ev) { int j = __ffs(ev) - 1; ev &= ev - 1; W.put(hbase + 11 + j, f, 1); }
+      while (ad) { int j = __ffs(ad) - 1; ad &= ad - 1; W.put(hbase + 22 + j, f, 1); }
+    }
+    const int gbase = own ? 251 : 303;
+    if (W.overlaps(gbase, gbase + 52)) {
+      uint32_t pr = (pw[2] >> 11) & 0x1FFFu, pa = pw[3] & 0x1FFFu;
+      uint32_t bb = (pw[3] >> 13) & 0x1FFFu, ba = (w0 >> 17) & 0x1FFFu;
+      while (pr) { int j = __ffs(pr) - 1; pr &= pr - 1; W.put(gbase + j, f, 1); }
+      while (pa) { int j = __ffs(pa) - 1; pa &= pa - 1; W.put(gbase + 13 + j, f, 1); }
+      while (bb) { int j = __ffs(bb) - 1; bb &= bb - 1; W.put(gbase + 26 + j, f, 1); }
+      while (ba) { int j = __ffs(ba) - 1; ba &= ba - 1; W.put(gbase + 39 + j, f, 1); }
+    }
+    if (W.overlaps(355, 455)) {
+      const int st = start_sq(id);
+      W.put(355 + (o == 0 ? st : 99 - st), f, 1);
+    }
+  }
+  // captured pieces: start squares (109-130) and death square x cause (131-250)
+  if (W.overlaps(109, 251)) {
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      int id = lane + 64 * h;
+      if (id >= kPieces) break;
+      const uint32_t w0 = piece_words(R, id)[0];
+      if (p_alive(w0)) continue;
+      const int t = p_type(w0);
+      if (t == kFlag) continue;
+      const bool own = owner(id) == o;
+      const int st = start_sq(id);
+      W.put((own ? 109 : 120) + (t == kBomb ? 10 : t), o == 0 ? st : 99 - st, 1);
+      if (t <= kMarshal) {
+        const int cause = (w0 >> 7) & 7, dsq = (w0 >> 10) & 127;
+        W.put((own ? 131 : 191) + 10 * (cause - 1) + t, o == 0 ? dsq : 99 - dsq, 1);
+      }
+    }
+  }
+  // recent moves (456-487), most recent first
+  if (W.overlaps(456, 488)) {
+    const int rc = R[kOffRingCount];
+    if (lane < rc) {
+      const int slot = (ply - 1 - lane) & 31;
+      const int fr = R[kOffRing + 2 * slot], tt = R[kOffRing + 2 * slot + 1];
+      W.put(456 + lane, o == 0 ? tt : 99 - tt, 0x01);
+      W.put(456 + lane, o == 0 ? fr : 99 - fr, 0xFF);
+    }
+  }
+}
+
+// Encode both observers of the game staged in R into obs (global, 97600 bytes),
+// building each segment of channels in the LDS image and streaming it out with
+// 16-byte stores.
+__device__ void encode_game(const uint8_t* R, uint8_t* slab, const Rules& rules, int segments,
+                            uint8_t* obs) {
+  const int lane = lane_id();
+  const int segc = seg_channels_for(segments);
+  uint8_t* img = slab + kSlabImage;
+  uint4* img4 = reinterpret_cast<uint4*>(img);
+#pragma unroll 1
+  for (int o = 0; o < 2; ++o) {
+#pragma unroll 1
+    for (int c_lo = 0; c_lo < kChannels; c_lo += segc) {
+      const int c_hi = c_lo + segc < kChannels ? c_lo + segc : kChannels;
+      const int chunks = (c_hi - c_lo) * 100 / 16;
+      for (int k = lane; k < chunks; k += 64) img4[k] = make_uint4(0, 0, 0, 0);
+      wave_sync();
+      SegWriter W{img, c_lo, c_hi};
+      scatter_segment(R, slab, rules, o, W);
+      wave_sync();
+      uint4* dst = reinterpret_cast<uint4*>(obs + o * kObsPerObserver + c_lo * 100);
+      for (int k = lane; k < chunks; k += 64) {
+        u32x4 v = reinterpret_cast<const u32x4*>(img4)[k];
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(dst) + k);
+      }
+      wave_sync();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- resampling
+// Hidden types of the player not to move redrawn uniformly among assignments
+// consistent with public information (paper section 2.5; belief samples are
+// replaced by this uniform model): first the Flag and Bombs among the unmoved
+// hidden pieces (partial Fisher-Yates in ascending id order, Flag first), then
+// the movable multiset shuffled over the remaining hidden pieces in ascending
+// id order.  Runs on lane 0.
+__device__ void resample_game(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_t new_id) {
+  const int lane = lane_id();
+  if (lane == 0) {
+    const int z = 1 - (int)(hdr_u32(R, kOffPly) & 1);
+    int known[12];
+    for (int t = 0; t < 12; ++t) known[t] = 0;
+    uint8_t* unmoved = scratch;        // up to 40 ids
+    uint8_t* list = scratch + 40;      // up to 40 types
+    int nu = 0;
+    for (int id = 40 * z; id < 40 * z + 40; ++id) {
+      uint32_t w0 = piece_words(R, id)[0];
+      if (!p_alive(w0) || p_revealed(w0)) known[p_type(w0)]++;
+      else if (!p_moved(w0)) unmoved[nu++] = (uint8_t)id;
+    }
+    const int nflag = initial_count(kFlag) - known[kFlag];
+    const int I = nflag + initial_count(kBomb) - known[kBomb];
+    WordStream ws;
+    ws.init(seed, new_id, hdr_u32(R, kOffEpisode), 3u);
+    for (int i = 0; i < I; ++i) {
+      int j = i + (int)mulshift(ws.next(), (uint32_t)(nu - i));
+      uint8_t tmp = unmoved[i];
+      unmoved[i] = unmoved[j];
+      unmoved[j] = tmp;
+    }
+    // mark the chosen immovable slots with their new types (bit 7 = assigned)
+    int L = 0;
+    for (int t = 0; t <= kMarshal; ++t)
+      for (int c = initial_count(t) - known[t]; c > 0; --c) list[L++] = (uint8_t)t;
+    for (int i = L - 1; i >= 1; --i) {
+      int j = (int)mulshift(ws.next(), (uint32_t)(i + 1));
+      uint8_t tmp = list[i];
+      list[i] = list[j];
+      list[j] = tmp;
+    }
+    // assign: immovables first (flag first), then the shuffled movables in id order
+    uint64_t immovable_mask = 0;   // bit (id - 40z)
+    for (int i = 0; i < I; ++i) {
+      int id = unmoved[i];
+      uint32_t* w = piece_words(R, id);
+      w[0] = (w[0] & ~15u) | (uint32_t)(i < nflag ? kFlag : kBomb);
+      immovable_mask |= 1ull << (id - 40 * z);
+    }
+    int k = 0;
+    for (int id = 40 * z; id < 40 * z + 40; ++id) {
+      uint32_t* w = piece_words(R, id);
+      if (!p_alive(w[0]) || p_revealed(w[0])) continue;
+      if ((immovable_mask >> (id - 40 * z)) & 1) continue;
+      w[0] = (w[0] & ~15u) | (uint32_t)list[k++];
+    }
+    set_hdr_u32(R, kOffGameId, new_id);
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------- validation
+// Well-formedness of a record that did not come from this engine: lakes
+// exactly on lake squares, board entries in range and alive, every alive piece
+// on exactly one square, each player's types form the initial multiset, only
+// movable pieces have moved, death squares/causes and ring squares in range,
+// counters in range.  Everything the kernels index by record contents is
+// covered, so a rejected record can never drive an out-of-range access.
+__device__ bool record_ok(const uint8_t* R) {
+  const int lane = lane_id();
+  bool bad = false;
+  int my_type[2] = {-1, -1};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    int s = lane + 64 * h;
+    if (s < kSquares) {
+      int v = board_at(R, s);
+      if (is_lake_sq(s) != (v == kLake)) bad = true;
+      if (v < -2 || v >= kPieces) bad = true;
+      if (v >= 0 && !p_alive(piece_words(R, v)[0])) bad = true;
+    }
+    int id = lane + 64 * h;
+    if (id < kPieces) {
+      uint32_t w0 = piece_words(R, id)[0];
+      int t = p_type(w0);
+      my_type[h] = t;
+      if (t > 11) bad = true;
+      if (p_moved(w0) && !movable_type(t)) bad = true;
+      const int cause = (w0 >> 7) & 7, dsq = (w0 >> 10) & 127;
+      if (p_alive(w0)) {
+        if (cause != 0 || dsq != 127) bad = true;
+        int n = 0;
+        for (int s2 = 0; s2 < kSquares; ++s2) n += board_at(R, s2) == id;
+        if (n != 1) bad = true;
+      } else {
+        if (cause < 1 || cause > 6 || dsq >= kSquares || !p_revealed(w0)) bad = true;
+      }
+    }
+    if (lane < 64) {
+      int b = R[kOffRing + lane];
+      if (b >= kSquares) bad = true;
+    }
+  }
+  // per-player type multiset equals the initial one (Table "pieces")
+  for (int t = 0; t < 12; ++t) {
+    uint64_t a = ballot(my_type[0] == t);   // ids 0..63
+    uint64_t b = ballot(my_type[1] == t);   // ids 64..79 in lanes 0..15
+    int red = __popcll(a & 0xFFFFFFFFFFull);
+    int blue = __popcll(a >> 40) + __popcll(b & 0xFFFFull);
+    if (red != initial_count(t) || blue != initial_count(t)) bad = true;
+  }
+  if (R[kOffRingCount] > 32 || R[kOffDone] > 1 || R[kOffReason] > 5 ||
+      (int)hdr_u32(R, kOffPly) < 0 || (int)hdr_u32(R, kOffPly) > 32767 ||
+      (int)hdr_u32(R, kOffBattleless) < 0)
+    bad = true;
+  return ballot(bad) == 0;
+}
+
+}  // namespace sg

@@ -1,0 +1,650 @@
+// libstratego.so: kernels and the C ABI declared in include/stratego.h.
+//
+// Plain engine: one launch per call (legal mask, sample, step, encode), one
+// wavefront per game, four games per 256-thread workgroup.
+// Fused engine: one persistent kernel per ply (mask -> sample -> encode ->
+// step), grid sized to the device's occupancy, tiles of G consecutive games
+// per workgroup, plies optionally replayed from a captured hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "stratego.h"
+#include "device.h"
+
+using namespace sg;
+
+namespace {
+
+enum : int { kDoMask = 1, kDoSample = 2, kDoEncode = 4, kDoStep = 8, kStepFromInput = 16 };
+constexpr int kFused = kDoMask | kDoSample | kDoEncode | kDoStep;
+constexpr int kMaxTimedPlies = 4096;
+
+struct PlyArgs {
+  uint8_t* states;
+  const int32_t* slots;
+  int32_t n;
+  int32_t total;      // games in the context (slot range)
+  int32_t out_base;   // index of this ply's row in [nplies][n] outputs
+  uint64_t* mask;
+  int16_t* num_legal;
+  const int16_t* actions_in;
+  int16_t* actions_out;
+  uint8_t* obs;
+  int8_t* done;
+  int8_t* outcome;
+  uint8_t* reason;
+  int16_t* ep_len;
+  int32_t* err;
+  unsigned long long* ts;
+  Rules rules;
+  int32_t games_per_tile;
+  int32_t segments;
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_ply(PlyArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
+  uint8_t* slab = smem + wave * slab_bytes_for(a.segments);
+  uint8_t* R = slab;
+  if (a.ts && threadIdx.x == 0) atomicMin(&a.ts[0], (unsigned long long)wall_clock64());
+  const int G = a.games_per_tile;
+  const int ntiles = (a.n + G - 1) / G;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int gi = wave; gi < G; gi += W) {
+      const int i = tile * G + gi;
+      if (i >= a.n) break;
+      const int slot = a.slots ? a.slots[i] : i;
+      if (slot < 0 || slot >= a.total) {
+        if (lane == 0) atomicMin(&a.err[1], i);
+        continue;
+      }
+      uint8_t* gstate = a.states + (size_t)slot * kRecordBytes;
+      load_record(R, gstate);
+      int action = -1;
+      if (MODE & kDoMask) {
+        uint64_t w[3];
+        const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
+        if (a.mask) {
+          uint64_t* m = a.mask + (size_t)i * kMaskWords;
+#pragma unroll
+          for (int g = 0; g < 3; ++g)
+            if (lane + 64 * g < kMaskWords) m[lane + 64 * g] = w[g];
+        }
+        if (a.num_legal && lane == 0) a.num_legal[i] = (int16_t)n;
+        if (MODE & kDoSample) {
+          action = sample_from_words(w, n, a.rules.seed, hdr_u32(R, kOffGameId),
+                                     hdr_u32(R, kOffPly), hdr_u32(R, kOffEpisode));
+          if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + i] = (int16_t)action;
+        }
+        wave_sync();
+      }
+      if (MODE & kStepFromInput) action = a.actions_in[i];
+      if (MODE & kDoEncode) {
+        if (a.obs) {
+          compute_probq(R, slab);
+          encode_game(R, slab, a.rules, a.segments, a.obs + (size_t)i * kObsPerGame);
+        }
+      }
+      if (MODE & kDoStep) {
+        StepOut o = step_game(R, slab + kSlabScratch, a.rules, action);
+        if (lane == 0) {
+          const size_t oi = (size_t)a.out_base + i;
+          if (a.done) a.done[oi] = (int8_t)o.done;
+          if (a.outcome) a.outcome[oi] = (int8_t)o.outcome;
+          if (a.reason) a.reason[oi] = (uint8_t)o.reason;
+          if (a.ep_len) a.ep_len[oi] = (int16_t)o.ep_len;
+          if (o.illegal) atomicMin(&a.err[0], slot);
+        }
+        wave_sync();
+        store_record(gstate, R);
+      }
+      wave_sync();
+    }
+  }
+  if (a.ts) {
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&a.ts[1], (unsigned long long)wall_clock64());
+  }
+}
+
+// Uniform legal action from a caller-supplied mask (plain engine).
+__global__ void __launch_bounds__(256) k_sample(const uint8_t* states, int32_t n, const uint64_t* mask,
+                                               const int16_t* num_legal, int16_t* actions, uint64_t seed) {
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (i >= n) return;
+  const uint8_t* g = states + (size_t)i * kRecordBytes;
+  const uint32_t game_id = *reinterpret_cast<const uint32_t*>(g + kOffGameId);
+  const uint32_t episode = *reinterpret_cast<const uint32_t*>(g + kOffEpisode);
+  const uint32_t ply = *reinterpret_cast<const uint32_t*>(g + kOffPly);
+  const bool done = g[kOffDone] != 0;
+  uint64_t w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int word = lane + 64 * k;
+    w[k] = word < kMaskWords ? mask[(size_t)i * kMaskWords + word] : 0ull;
+  }
+  const int nl = done ? 0 : num_legal[i];
+  const int action = sample_from_words(w, nl, seed, game_id, ply, episode);
+  if (lane == 0) actions[i] = (int16_t)action;
+}
+
+// Fresh setups (episode 0) for the listed slots.
+__global__ void __launch_bounds__(256) k_reset_fresh(uint8_t* states, const int32_t* slots, int32_t n,
+                                                    int32_t total, Rules rules, uint32_t game_id_base,
+                                                    int32_t* err) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (i >= n) return;
+  uint8_t* slab = smem + wave * kSlabImage;
+  const int slot = slots ? slots[i] : i;
+  if (slot < 0 || slot >= total) {
+    if (lane_id() == 0) atomicMin(&err[1], i);
+    return;
+  }
+  reset_game(slab, slab + kSlabScratch, rules, game_id_base + (uint32_t)slot, 0u, 0u);
+  store_record(states + (size_t)slot * kRecordBytes, slab);
+}
+
+// Import caller records into the listed slots after a well-formedness check.
+__global__ void __launch_bounds__(256) k_import(uint8_t* states, const int32_t* slots, int32_t n,
+                                               int32_t total, const uint8_t* src, int32_t* err) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (i >= n) return;
+  uint8_t* R = smem + wave * kSlabImage;
+  const int slot = slots ? slots[i] : i;
+  if (slot < 0 || slot >= total) {
+    if (lane_id() == 0) atomicMin(&err[1], i);
+    return;
+  }
+  load_record(R, src + (size_t)i * kRecordBytes);
+  if (record_ok(R)) store_record(states + (size_t)slot * kRecordBytes, R);
+  else if (lane_id() == 0) atomicMin(&err[1], slot);
+}
+
+// Slot k = i*per + j receives a resample of source record i.
+__global__ void __launch_bounds__(256) k_resample(uint8_t* states, const uint8_t* src, int32_t nsrc,
+                                                 int32_t per, uint64_t seed, uint32_t id_base,
+                                                 int32_t* err) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int k = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (k >= nsrc * per) return;
+  uint8_t* slab = smem + wave * kSlabImage;
+  load_record(slab, src + (size_t)(k / per) * kRecordBytes);
+  if (!record_ok(slab)) {
+    if (lane_id() == 0) atomicMin(&err[1], k);
+    return;
+  }
+  resample_game(slab, slab + kSlabScratch, seed, id_base + (uint32_t)k);
+  store_record(states + (size_t)k * kRecordBytes, slab);
+}
+
+__global__ void k_ts_init(unsigned long long* ts, int32_t nplies) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nplies) {
+    ts[2 * i] = ~0ull;
+    ts[2 * i + 1] = 0ull;
+  }
+}
+
+__global__ void k_ts_convert(const unsigned long long* ts, int32_t nplies, double ns_per_tick,
+                             int64_t* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nplies) out[i] = (int64_t)((double)(ts[2 * i + 1] - ts[2 * i]) * ns_per_tick);
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+struct GraphEntry {
+  int32_t nplies, G, S;
+  const void* ptrs[9];
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct stratego_ctx {
+  stratego_config cfg;
+  hipStream_t stream;
+  hipStream_t capture_stream;
+  int device;
+  int num_cu;
+  size_t max_lds;
+  double ns_per_tick;
+  uint8_t* states;
+  uint8_t* backup;   // copy of the states while the autotuner runs
+  int32_t* err;
+  unsigned long long* ts;
+  int64_t steps;
+  int G, S;
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+inline Rules rules_of(const stratego_ctx* c) {
+  Rules r;
+  r.seed = c->cfg.seed;
+  r.k_battleless = c->cfg.k_battleless;
+  r.max_moves = c->cfg.max_moves;
+  r.auto_reset = c->cfg.auto_reset;
+  return r;
+}
+
+inline int grid_for(int n, int per_block) { return (n + per_block - 1) / per_block; }
+
+bool valid_tiling(int G, int S) {
+  return (G == 1 || G == 2 || G == 4 || G == 8 || G == 16) &&
+         (S == 1 || S == 2 || S == 4 || S == 8);
+}
+
+inline int waves_for(int G) { return G < 4 ? G : 4; }
+
+// Dynamic LDS of one fused-engine workgroup.
+inline size_t lds_for(int G, int S) { return (size_t)waves_for(G) * slab_bytes_for(S); }
+
+int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent) {
+  const int W = (mode == kFused) ? waves_for(G) : 4;
+  const int tile = (mode == kFused) ? G : 4;
+  a.games_per_tile = tile;
+  a.segments = S;
+  const size_t lds = (size_t)W * slab_bytes_for(S);
+  if (lds > c->max_lds) return STRATEGO_E_INVAL;
+  int ntiles = grid_for(a.n, tile);
+  int grid = ntiles;
+  const void* fn = nullptr;
+  switch (mode) {
+    case kFused: fn = reinterpret_cast<const void*>(&k_ply<kFused>); break;
+    case kDoMask: fn = reinterpret_cast<const void*>(&k_ply<kDoMask>); break;
+    case kDoEncode: fn = reinterpret_cast<const void*>(&k_ply<kDoEncode>); break;
+    case kDoStep | kStepFromInput: fn = reinterpret_cast<const void*>(&k_ply<kDoStep | kStepFromInput>); break;
+    default: return STRATEGO_E_INVAL;
+  }
+  if (persistent) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * W, lds) != hipSuccess || per_cu <= 0)
+      return STRATEGO_E_INVAL;
+    int cap = per_cu * c->num_cu;
+    if (grid > cap) grid = cap;
+  }
+  if (grid <= 0) return STRATEGO_OK;
+  switch (mode) {
+    case kFused: hipLaunchKernelGGL(k_ply<kFused>, dim3(grid), dim3(64 * W), lds, s, a); break;
+    case kDoMask: hipLaunchKernelGGL(k_ply<kDoMask>, dim3(grid), dim3(64 * W), lds, s, a); break;
+    case kDoEncode: hipLaunchKernelGGL(k_ply<kDoEncode>, dim3(grid), dim3(64 * W), lds, s, a); break;
+    default:
+      hipLaunchKernelGGL((k_ply<kDoStep | kStepFromInput>), dim3(grid), dim3(64 * W), lds, s, a);
+      break;
+  }
+  return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+PlyArgs base_args(stratego_ctx* c) {
+  PlyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.states = c->states;
+  a.n = c->cfg.num_games;
+  a.total = c->cfg.num_games;
+  a.err = c->err;
+  a.rules = rules_of(c);
+  return a;
+}
+
+int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t* slots, int32_t n,
+                  uint64_t* mask, int16_t* num_legal, int16_t* actions, uint8_t* obs, int8_t* done,
+                  int8_t* outcome, uint8_t* reason, int16_t* ep_len, bool timed, int G, int S) {
+  if (timed) {
+    hipLaunchKernelGGL(k_ts_init, dim3(grid_for(nplies, 256)), dim3(256), 0, s, c->ts, nplies);
+    if (hipGetLastError() != hipSuccess) return STRATEGO_E_HIP;
+  }
+  for (int p = 0; p < nplies; ++p) {
+    PlyArgs a = base_args(c);
+    a.slots = slots;
+    a.n = n;
+    a.out_base = p * n;
+    a.mask = mask;
+    a.num_legal = num_legal;
+    a.actions_out = actions;
+    a.obs = obs;
+    a.done = done;
+    a.outcome = outcome;
+    a.reason = reason;
+    a.ep_len = ep_len;
+    a.ts = timed ? c->ts + 2 * p : nullptr;
+    int rc = launch_ply(c, s, kFused, a, G, S, true);
+    if (rc != STRATEGO_OK) return rc;
+  }
+  return STRATEGO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stratego_strerror(int code) {
+  switch (code) {
+    case STRATEGO_OK: return "ok";
+    case STRATEGO_E_INVAL: return "invalid argument";
+    case STRATEGO_E_NOMEM: return "device allocation failed";
+    case STRATEGO_E_HIP: return "HIP runtime error";
+    case STRATEGO_E_ILLEGAL_ACTION: return "illegal action for a live game";
+    case STRATEGO_E_BAD_STATE: return "malformed state record";
+    default: return "unknown error";
+  }
+}
+
+int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** out) {
+  if (!cfg || !out) return STRATEGO_E_INVAL;
+  *out = nullptr;
+  if (cfg->num_games <= 0 || cfg->k_battleless <= 0 || cfg->max_moves <= 0 ||
+      cfg->max_moves > 32767 || (cfg->auto_reset != 0 && cfg->auto_reset != 1))
+    return STRATEGO_E_INVAL;
+  int G = cfg->games_per_wg ? cfg->games_per_wg : 4;
+  int S = cfg->lds_segments ? cfg->lds_segments : 4;
+  if (!valid_tiling(G, S)) return STRATEGO_E_INVAL;
+  stratego_ctx* c = new (std::nothrow) stratego_ctx();
+  if (!c) return STRATEGO_E_NOMEM;
+  c->cfg = *cfg;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->G = G;
+  c->S = S;
+  c->steps = 0;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return STRATEGO_E_HIP; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; return STRATEGO_E_HIP; }
+  c->num_cu = prop.multiProcessorCount;
+  c->max_lds = prop.sharedMemPerBlock;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0)
+    khz = 100000;
+  c->ns_per_tick = 1.0e6 / (double)khz;
+  const size_t nbytes = (size_t)cfg->num_games * kRecordBytes;
+  if (hipMalloc(&c->states, nbytes) != hipSuccess) { delete c; return STRATEGO_E_NOMEM; }
+  if (hipMalloc(&c->backup, nbytes) != hipSuccess) {
+    (void)hipFree(c->states); delete c; return STRATEGO_E_NOMEM;
+  }
+  if (hipMalloc(&c->err, 2 * sizeof(int32_t)) != hipSuccess) {
+    (void)hipFree(c->states); (void)hipFree(c->backup); delete c; return STRATEGO_E_NOMEM;
+  }
+  if (hipMalloc(&c->ts, 2 * sizeof(unsigned long long) * kMaxTimedPlies) != hipSuccess) {
+    (void)hipFree(c->states); (void)hipFree(c->backup); (void)hipFree(c->err); delete c;
+    return STRATEGO_E_NOMEM;
+  }
+  if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(c->states); (void)hipFree(c->backup); (void)hipFree(c->err); (void)hipFree(c->ts);
+    delete c;
+    return STRATEGO_E_HIP;
+  }
+  // kernels whose dynamic LDS may exceed the default limit
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ply<kFused>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->max_lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ply<kDoEncode>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->max_lds);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->err, 2, INT_MAX);
+  int rc = stratego_reset(c, nullptr, cfg->num_games, nullptr);
+  if (rc != STRATEGO_OK) { stratego_destroy(c); return rc; }
+  *out = c;
+  return STRATEGO_OK;
+}
+
+int stratego_reset(stratego_ctx* c, const int32_t* slots, int32_t n, const void* states) {
+  if (!c || n < 0 || n > c->cfg.num_games) return STRATEGO_E_INVAL;
+  if (n == 0) return STRATEGO_OK;
+  const int grid = grid_for(n, 4);
+  if (states) {
+    hipLaunchKernelGGL(k_import, dim3(grid), dim3(256), 4 * kSlabImage, c->stream, c->states, slots, n,
+                       c->cfg.num_games, reinterpret_cast<const uint8_t*>(states), c->err);
+  } else {
+    hipLaunchKernelGGL(k_reset_fresh, dim3(grid), dim3(256), 4 * kSlabImage, c->stream, c->states, slots,
+                       n, c->cfg.num_games, rules_of(c), c->cfg.game_id_base, c->err);
+  }
+  return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+int stratego_legal_mask(stratego_ctx* c, uint64_t* mask, int16_t* num_legal) {
+  if (!c || !mask) return STRATEGO_E_INVAL;
+  PlyArgs a = base_args(c);
+  a.mask = mask;
+  a.num_legal = num_legal;
+  return launch_ply(c, c->stream, kDoMask, a, 4, 8, false);
+}
+
+int stratego_sample_actions(stratego_ctx* c, const uint64_t* mask, const int16_t* num_legal,
+                            int16_t* actions) {
+  if (!c || !mask || !num_legal || !actions) return STRATEGO_E_INVAL;
+  hipLaunchKernelGGL(k_sample, dim3(grid_for(c->cfg.num_games, 4)), dim3(256), 0, c->stream, c->states,
+                     c->cfg.num_games, mask, num_legal, actions, c->cfg.seed);
+  return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+int stratego_step(stratego_ctx* c, const int16_t* actions, int8_t* done, int8_t* outcome,
+                  uint8_t* reason, int16_t* ep_len) {
+  if (!c || !actions) return STRATEGO_E_INVAL;
+  PlyArgs a = base_args(c);
+  a.actions_in = actions;
+  a.done = done;
+  a.outcome = outcome;
+  a.reason = reason;
+  a.ep_len = ep_len;
+  int rc = launch_ply(c, c->stream, kDoStep | kStepFromInput, a, 4, 8, false);
+  if (rc == STRATEGO_OK) c->steps += c->cfg.num_games;
+  return rc;
+}
+
+int stratego_encode_obs(stratego_ctx* c, uint8_t* obs) {
+  if (!c || !obs) return STRATEGO_E_INVAL;
+  PlyArgs a = base_args(c);
+  a.obs = obs;
+  return launch_ply(c, c->stream, kDoEncode, a, 4, 4, false);
+}
+
+int stratego_export_states(stratego_ctx* c, void* states) {
+  if (!c || !states) return STRATEGO_E_INVAL;
+  return hipMemcpyAsync(states, c->states, (size_t)c->cfg.num_games * kRecordBytes,
+                        hipMemcpyDeviceToDevice, c->stream) == hipSuccess
+             ? STRATEGO_OK
+             : STRATEGO_E_HIP;
+}
+
+int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t* num_legal,
+                       int16_t* actions, uint8_t* obs, int8_t* done, int8_t* outcome, uint8_t* reason,
+                       int16_t* ep_len, int32_t use_graph, int64_t* ply_ns) {
+  if (!c || nplies < 0) return STRATEGO_E_INVAL;
+  if (ply_ns && nplies > kMaxTimedPlies) return STRATEGO_E_INVAL;
+  if (nplies == 0) return STRATEGO_OK;
+  const bool timed = ply_ns != nullptr;
+  const int n = c->cfg.num_games;
+  if (!use_graph) {
+    int rc = enqueue_plies(c, c->stream, nplies, nullptr, n, mask, num_legal, actions, obs, done,
+                           outcome, reason, ep_len, timed, c->G, c->S);
+    if (rc != STRATEGO_OK) return rc;
+  } else {
+    const void* key[9] = {mask, num_legal, actions, obs, done, outcome, reason, ep_len,
+                          timed ? (const void*)c->ts : nullptr};
+    hipGraphExec_t exec = nullptr;
+    for (auto& e : c->graphs) {
+      if (e.nplies == nplies && e.G == c->G && e.S == c->S && std::memcmp(e.ptrs, key, sizeof(key)) == 0) {
+        exec = e.exec;
+        break;
+      }
+    }
+    if (!exec) {
+      hipGraph_t graph;
+      if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return STRATEGO_E_HIP;
+      int rc = enqueue_plies(c, c->capture_stream, nplies, nullptr, n, mask, num_legal, actions, obs,
+                             done, outcome, reason, ep_len, timed, c->G, c->S);
+      hipError_t ec = hipStreamEndCapture(c->capture_stream, &graph);
+      if (rc != STRATEGO_OK) { if (ec == hipSuccess) (void)hipGraphDestroy(graph); return rc; }
+      if (ec != hipSuccess) return STRATEGO_E_HIP;
+      if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return STRATEGO_E_HIP;
+      }
+      (void)hipGraphDestroy(graph);
+      if (c->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+      }
+      GraphEntry e;
+      e.nplies = nplies;
+      e.G = c->G;
+      e.S = c->S;
+      std::memcpy(e.ptrs, key, sizeof(key));
+      e.exec = exec;
+      c->graphs.push_back(e);
+    }
+    if (hipGraphLaunch(exec, c->stream) != hipSuccess) return STRATEGO_E_HIP;
+  }
+  if (timed) {
+    hipLaunchKernelGGL(k_ts_convert, dim3(grid_for(nplies, 256)), dim3(256), 0, c->stream, c->ts, nplies,
+                       c->ns_per_tick, ply_ns);
+    if (hipGetLastError() != hipSuccess) return STRATEGO_E_HIP;
+  }
+  c->steps += (int64_t)nplies * n;
+  return STRATEGO_OK;
+}
+
+int stratego_run_plies_slots(stratego_ctx* c, const int32_t* slots, int32_t nslots, int32_t nplies,
+                             uint64_t* mask, int16_t* actions, uint8_t* obs, int8_t* done,
+                             int8_t* outcome, uint8_t* reason, int16_t* ep_len) {
+  if (!c || !slots || nslots < 0 || nslots > c->cfg.num_games || nplies < 0) return STRATEGO_E_INVAL;
+  if (nslots == 0 || nplies == 0) return STRATEGO_OK;
+  int rc = enqueue_plies(c, c->stream, nplies, slots, nslots, mask, nullptr, actions, obs, done, outcome,
+                         reason, ep_len, false, c->G, c->S);
+  if (rc == STRATEGO_OK) c->steps += (int64_t)nplies * nslots;
+  return rc;
+}
+
+int stratego_reset_resampled(stratego_ctx* c, const void* src, int32_t nsrc, int32_t per,
+                             uint32_t game_id_base) {
+  if (!c || !src || nsrc <= 0 || per <= 0 || (int64_t)nsrc * per > c->cfg.num_games)
+    return STRATEGO_E_INVAL;
+  const int total = nsrc * per;
+  hipLaunchKernelGGL(k_resample, dim3(grid_for(total, 4)), dim3(256), 4 * kSlabImage, c->stream, c->states,
+                     reinterpret_cast<const uint8_t*>(src), nsrc, per, c->cfg.seed, game_id_base, c->err);
+  return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+int stratego_get_tiling(stratego_ctx* c, int32_t* G, int32_t* S) {
+  if (!c) return STRATEGO_E_INVAL;
+  if (G) *G = c->G;
+  if (S) *S = c->S;
+  return STRATEGO_OK;
+}
+
+int stratego_set_tiling(stratego_ctx* c, int32_t G, int32_t S) {
+  if (!c || !valid_tiling(G, S) || lds_for(G, S) > c->max_lds) return STRATEGO_E_INVAL;
+  c->G = G;
+  c->S = S;
+  return STRATEGO_OK;
+}
+
+int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t plies,
+                      stratego_tune_entry* report, int32_t max_entries, int32_t* n_entries) {
+  if (!c || plies <= 0) return STRATEGO_E_INVAL;
+  const int n = c->cfg.num_games;
+  uint8_t* backup = c->backup;
+  const size_t nbytes = (size_t)n * kRecordBytes;
+  // the tuning plies advance the games; they are restored afterwards so that
+  // results do not depend on whether tuning ran
+  if (hipMemcpyAsync(backup, c->states, nbytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return STRATEGO_E_HIP;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int Gs[5] = {1, 2, 4, 8, 16};
+  const int Ss[4] = {1, 2, 4, 8};
+  int best_G = c->G, best_S = c->S, count = 0;
+  float best = 1e30f;
+  int rc = STRATEGO_OK;
+  for (int gi = 0; gi < 5 && rc == STRATEGO_OK; ++gi) {
+    for (int si = 0; si < 4 && rc == STRATEGO_OK; ++si) {
+      const int G = Gs[gi], S = Ss[si];
+      if (lds_for(G, S) > c->max_lds) continue;
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_ply<kFused>),
+                                                       64 * waves_for(G), lds_for(G, S)) != hipSuccess ||
+          per_cu <= 0)
+        continue;
+      // warm-up ply, then the timed plies
+      rc = enqueue_plies(c, c->stream, 1, nullptr, n, mask, nullptr, nullptr, obs, nullptr, nullptr, nullptr,
+                         nullptr, false, G, S);
+      if (rc != STRATEGO_OK) break;
+      (void)hipEventRecord(e0, c->stream);
+      rc = enqueue_plies(c, c->stream, plies, nullptr, n, mask, nullptr, nullptr, obs, nullptr, nullptr,
+                         nullptr, nullptr, false, G, S);
+      (void)hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = STRATEGO_E_HIP; break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const float us = 1000.f * ms / (float)plies;
+      if (report && count < max_entries) {
+        report[count].games_per_wg = G;
+        report[count].lds_segments = S;
+        report[count].us_per_ply = us;
+      }
+      ++count;
+      if (us < best) { best = us; best_G = G; best_S = S; }
+    }
+  }
+  (void)hipMemcpyAsync(c->states, backup, nbytes, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != STRATEGO_OK) return rc;
+  c->G = best_G;
+  c->S = best_S;
+  if (n_entries) *n_entries = count;
+  return STRATEGO_OK;
+}
+
+int stratego_get_error(stratego_ctx* c, int32_t* first_bad_slot) {
+  if (!c) return STRATEGO_E_INVAL;
+  int32_t h[2];
+  if (hipMemcpyAsync(h, c->err, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return STRATEGO_E_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return STRATEGO_E_HIP;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->err, 2, INT_MAX);
+  int rc = STRATEGO_OK;
+  int32_t slot = -1;
+  if (h[0] != INT_MAX) { rc = STRATEGO_E_ILLEGAL_ACTION; slot = h[0]; }
+  else if (h[1] != INT_MAX) { rc = STRATEGO_E_BAD_STATE; slot = h[1]; }
+  if (first_bad_slot) *first_bad_slot = slot;
+  return rc;
+}
+
+int stratego_current_step(stratego_ctx* c, int64_t* steps) {
+  if (!c || !steps) return STRATEGO_E_INVAL;
+  *steps = c->steps;
+  return STRATEGO_OK;
+}
+
+int stratego_destroy(stratego_ctx* c) {
+  if (!c) return STRATEGO_E_INVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
+  c->graphs.clear();
+  (void)hipStreamDestroy(c->capture_stream);
+  (void)hipFree(c->states);
+  (void)hipFree(c->backup);
+  (void)hipFree(c->err);
+  (void)hipFree(c->ts);
+  delete c;
+  return STRATEGO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+"""Python binding of libstratego.so (argument marshalling only).
+
+Every function mirrors the C call of the same name in include/stratego.h.
+Device buffers are torch tensors on the GPU; the HIP stream is torch's
+current stream.  All game computation happens in the library's kernels: if the
+library is missing the import fails loudly, there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libstratego.so")
+
+OK = 0
+E_INVAL = -1
+E_NOMEM = -2
+E_HIP = -3
+E_ILLEGAL_ACTION = -4
+E_BAD_STATE = -5
+NUM_CHANNELS = 488
+MASK_WORDS = 157
+RECORD_BYTES = 1536
+OBS_BYTES_PER_GAME = 97600
+
+FUNCTIONS = [
+    "stratego_init", "stratego_reset", "stratego_legal_mask", "stratego_sample_actions",
+    "stratego_step", "stratego_encode_obs", "stratego_export_states", "stratego_run_plies",
+    "stratego_run_plies_slots", "stratego_reset_resampled", "stratego_autotune",
+    "stratego_get_tiling", "stratego_set_tiling", "stratego_get_error", "stratego_current_step",
+    "stratego_destroy", "stratego_strerror",
+]
+
+
+class StrategoConfig(ctypes.Structure):
+    _fields_ = [("num_games", ctypes.c_int32), ("k_battleless", ctypes.c_int32),
+                ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("game_id_base", ctypes.c_uint32),
+                ("games_per_wg", ctypes.c_int32), ("lds_segments", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("games_per_wg", ctypes.c_int32), ("lds_segments", ctypes.c_int32),
+                ("us_per_ply", ctypes.c_double)]
+
+
+class StrategoError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libstratego.so (without touching the GPU)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.stratego_init.argtypes = [ctypes.POINTER(StrategoConfig), P, ctypes.POINTER(P)]
+    L.stratego_reset.argtypes = [P, P, I32, P]
+    L.stratego_legal_mask.argtypes = [P, P, P]
+    L.stratego_sample_actions.argtypes = [P, P, P, P]
+    L.stratego_step.argtypes = [P, P, P, P, P, P]
+    L.stratego_encode_obs.argtypes = [P, P]
+    L.stratego_export_states.argtypes = [P, P]
+    L.stratego_run_plies.argtypes = [P, I32, P, P, P, P, P, P, P, P, I32, P]
+    L.stratego_run_plies_slots.argtypes = [P, P, I32, I32, P, P, P, P, P, P, P]
+    L.stratego_reset_resampled.argtypes = [P, P, I32, I32, ctypes.c_uint32]
+    L.stratego_autotune.argtypes = [P, P, P, I32, ctypes.POINTER(TuneEntry), I32,
+                                    ctypes.POINTER(I32)]
+    L.stratego_get_tiling.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    L.stratego_set_tiling.argtypes = [P, I32, I32]
+    L.stratego_get_error.argtypes = [P, ctypes.POINTER(I32)]
+    L.stratego_current_step.argtypes = [P, ctypes.POINTER(I64)]
+    L.stratego_destroy.argtypes = [P]
+    L.stratego_strerror.argtypes = [ctypes.c_int]
+    L.stratego_strerror.restype = ctypes.c_char_p
+    for f in FUNCTIONS:
+        if f != "stratego_strerror":
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def strerror(code):
+    return load_library().stratego_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise StrategoError(rc, what)
+
+
+def _ptr(t, dtype=None, numel=None, name="buffer"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ C-ABI mirrors
+def stratego_init(num_games, seed, k_battleless=100, max_moves=4000, auto_reset=False,
+                  game_id_base=0, games_per_wg=0, lds_segments=0):
+    cfg = StrategoConfig(int(num_games), int(k_battleless), int(max_moves), int(bool(auto_reset)),
+                         int(seed), int(game_id_base), int(games_per_wg), int(lds_segments), 0)
+    ctx = ctypes.c_void_p()
+    _check(load_library().stratego_init(ctypes.byref(cfg), _stream(), ctypes.byref(ctx)),
+           "stratego_init")
+    _ctx_games[ctx.value] = int(num_games)
+    return ctx
+
+
+def stratego_reset(ctx, slots=None, n=None, states=None):
+    if n is None:
+        n = slots.numel() if slots is not None else (states.shape[0] if states is not None else None)
+    _check(load_library().stratego_reset(ctx, _ptr(slots, torch.int32, n, "slots"), int(n),
+                                         _ptr(states, torch.uint8, n * RECORD_BYTES, "states")),
+           "stratego_reset")
+
+
+def stratego_legal_mask(ctx, mask, num_legal=None):
+    n = _num_games(ctx)
+    _check(load_library().stratego_legal_mask(ctx, _ptr(mask, torch.int64, n and n * MASK_WORDS, "mask"),
+                                              _ptr(num_legal, torch.int16, n, "num_legal")),
+           "stratego_legal_mask")
+
+
+def stratego_sample_actions(ctx, mask, num_legal, actions):
+    n = _num_games(ctx)
+    _check(load_library().stratego_sample_actions(
+        ctx, _ptr(mask, torch.int64, n and n * MASK_WORDS, "mask"),
+        _ptr(num_legal, torch.int16, n, "num_legal"),
+        _ptr(actions, torch.int16, n, "actions")), "stratego_sample_actions")
+
+
+def stratego_step(ctx, actions, done=None, outcome=None, reason=None, ep_len=None):
+    n = _num_games(ctx)
+    _check(load_library().stratego_step(
+        ctx, _ptr(actions, torch.int16, n, "actions"), _ptr(done, torch.int8, n, "done"),
+        _ptr(outcome, torch.int8, n, "outcome"), _ptr(reason, torch.uint8, n, "reason"),
+        _ptr(ep_len, torch.int16, n, "ep_len")), "stratego_step")
+
+
+def stratego_encode_obs(ctx, obs):
+    n = _num_games(ctx)
+    _check(load_library().stratego_encode_obs(
+        ctx, _ptr(obs, torch.uint8, n and n * OBS_BYTES_PER_GAME, "obs")), "stratego_encode_obs")
+
+
+def stratego_export_states(ctx, states):
+    n = _num_games(ctx)
+    _check(load_library().stratego_export_states(
+        ctx, _ptr(states, torch.uint8, n and n * RECORD_BYTES, "states")), "stratego_export_states")
+
+
+def _num_games(ctx):
+    return _ctx_games.get(ctx.value)
+
+
+_ctx_games = {}
+
+
+def stratego_run_plies(ctx, nplies, mask=None, num_legal=None, actions=None, obs=None, done=None,
+                       outcome=None, reason=None, ep_len=None, use_graph=False, ply_ns=None):
+    n = _num_games(ctx)
+    per = None if n is None else int(nplies) * n
+    _check(load_library().stratego_run_plies(
+        ctx, int(nplies), _ptr(mask, torch.int64, n and n * MASK_WORDS, "mask"),
+        _ptr(num_legal, torch.int16, n, "num_legal"), _ptr(actions, torch.int16, per, "actions"),
+        _ptr(obs, torch.uint8, n and n * OBS_BYTES_PER_GAME, "obs"),
+        _ptr(done, torch.int8, per, "done"), _ptr(outcome, torch.int8, per, "outcome"),
+        _ptr(reason, torch.uint8, per, "reason"), _ptr(ep_len, torch.int16, per, "ep_len"),
+        int(bool(use_graph)), _ptr(ply_ns, torch.int64, int(nplies), "ply_ns")),
+        "stratego_run_plies")
+
+
+def stratego_run_plies_slots(ctx, slots, nplies, mask=None, actions=None, obs=None, done=None,
+                             outcome=None, reason=None, ep_len=None):
+    m = int(slots.numel())
+    per = int(nplies) * m
+    _check(load_library().stratego_run_plies_slots(
+        ctx, _ptr(slots, torch.int32, m, "slots"), m, int(nplies),
+        _ptr(mask, torch.int64, m * MASK_WORDS, "mask"), _ptr(actions, torch.int16, per, "actions"),
+        _ptr(obs, torch.uint8, m * OBS_BYTES_PER_GAME, "obs"), _ptr(done, torch.int8, per, "done"),
+        _ptr(outcome, torch.int8, per, "outcome"), _ptr(reason, torch.uint8, per, "reason"),
+        _ptr(ep_len, torch.int16, per, "ep_len")), "stratego_run_plies_slots")
+
+
+def stratego_reset_resampled(ctx, src_states, per, game_id_base=0):
+    nsrc = src_states.shape[0]
+    _check(load_library().stratego_reset_resampled(
+        ctx, _ptr(src_states, torch.uint8, nsrc * RECORD_BYTES, "src_states"), int(nsrc), int(per),
+        int(game_id_base)), "stratego_reset_resampled")
+
+
+def stratego_autotune(ctx, obs, mask, plies=3, max_entries=32):
+    rep = (TuneEntry * max_entries)()
+    n = ctypes.c_int32()
+    _check(load_library().stratego_autotune(ctx, _ptr(obs, torch.uint8, None, "obs"),
+                                            _ptr(mask, torch.int64, None, "mask"), int(plies), rep,
+                                            max_entries, ctypes.byref(n)), "stratego_autotune")
+    return [(rep[i].games_per_wg, rep[i].lds_segments, rep[i].us_per_ply) for i in range(n.value)]
+
+
+def stratego_get_tiling(ctx):
+    g, s = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().stratego_get_tiling(ctx, ctypes.byref(g), ctypes.byref(s)),
+           "stratego_get_tiling")
+    return g.value, s.value
+
+
+def stratego_set_tiling(ctx, games_per_wg, lds_segments):
+    _check(load_library().stratego_set_tiling(ctx, int(games_per_wg), int(lds_segments)),
+           "stratego_set_tiling")
+
+
+def stratego_get_error(ctx):
+    slot = ctypes.c_int32()
+    rc = load_library().stratego_get_error(ctx, ctypes.byref(slot))
+    return rc, slot.value
+
+
+def stratego_current_step(ctx):
+    v = ctypes.c_int64()
+    _check(load_library().stratego_current_step(ctx, ctypes.byref(v)), "stratego_current_step")
+    return v.value
+
+
+def stratego_destroy(ctx):
+    _check(load_library().stratego_destroy(ctx), "stratego_destroy")
+    _ctx_games.pop(ctx.value, None)
+
+
+# ------------------------------------------------------------------ convenience
+class Engine:
+    """N games on the current GPU with preallocated output tensors."""
+
+    def __init__(self, num_games, seed, k_battleless=100, max_moves=1000, auto_reset=False,
+                 game_id_base=0, games_per_wg=0, lds_segments=0, device="cuda"):
+        self.n = int(num_games)
+        self.device = torch.device(device)
+        self.ctx = stratego_init(num_games, seed, k_battleless, max_moves, auto_reset,
+                                 game_id_base, games_per_wg, lds_segments)
+        n, d = self.n, self.device
+        self.mask = torch.empty((n, MASK_WORDS), dtype=torch.int64, device=d)
+        self.num_legal = torch.empty(n, dtype=torch.int16, device=d)
+        self.actions = torch.empty(n, dtype=torch.int16, device=d)
+        self.done = torch.empty(n, dtype=torch.int8, device=d)
+        self.outcome = torch.empty(n, dtype=torch.int8, device=d)
+        self.reason = torch.empty(n, dtype=torch.uint8, device=d)
+        self.ep_len = torch.empty(n, dtype=torch.int16, device=d)
+        self._obs = None
+
+    @property
+    def obs(self):
+        if self._obs is None:
+            self._obs = torch.empty((self.n, 2, NUM_CHANNELS, 10, 10), dtype=torch.uint8,
+                                    device=self.device)
+        return self._obs
+
+    def legal_mask(self):
+        stratego_legal_mask(self.ctx, self.mask, self.num_legal)
+        return self.mask, self.num_legal
+
+    def sample(self):
+        stratego_sample_actions(self.ctx, self.mask, self.num_legal, self.actions)
+        return self.actions
+
+    def step(self, actions=None):
+        stratego_step(self.ctx, self.actions if actions is None else actions, self.done,
+                      self.outcome, self.reason, self.ep_len)
+        return self.done, self.outcome, self.reason, self.ep_len
+
+    def encode(self):
+        stratego_encode_obs(self.ctx, self.obs)
+        return self.obs
+
+    def export(self):
+        out = torch.empty((self.n, RECORD_BYTES), dtype=torch.uint8, device=self.device)
+        stratego_export_states(self.ctx, out)
+        return out
+
+    def load(self, records, slots=None):
+        stratego_reset(self.ctx, slots, records.shape[0], records)
+
+    def reset(self, slots=None, n=None):
+        stratego_reset(self.ctx, slots, self.n if n is None and slots is None else n, None)
+
+    def error(self):
+        return stratego_get_error(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            stratego_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,310 @@
+"""GPU engine vs CPU oracle, bit-exact (integer work: states, masks, actions,
+observations and outcomes must be identical)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from positions import header, make_record, sq
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2511_07312_amd import engine as E  # noqa: E402
+
+
+def cpu(t):
+    a = t.cpu().numpy()
+    return a.view(np.uint64) if a.dtype == np.int64 and a.ndim == 2 and a.shape[-1] == 157 else a
+
+
+def assert_same(name, got, want):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    assert got.shape == want.shape, (name, got.shape, want.shape)
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        raise AssertionError(f"{name}: {len(bad)} mismatches, first at {bad[:5].tolist()}")
+
+
+# ---------------------------------------------------------------- plain engine
+def test_plain_engine_256_games_200_plies():
+    """Plain per-step kernels: 256 games, 200 plies, no auto-reset; every mask,
+    action, observation, step output and state compared every ply."""
+    n, seed = 256, 1
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000)
+    ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000)
+    assert_same("initial states", cpu(eng.export()), ref.export())
+    for ply in range(200):
+        eng.legal_mask()
+        eng.sample()
+        eng.encode()
+        eng.step()
+        m, nl = ref.mask()
+        a = ref.sample(m, nl)
+        obs = ref.encode()
+        r = ref.step(a)
+        assert_same(f"mask@{ply}", cpu(eng.mask), m)
+        assert_same(f"num_legal@{ply}", cpu(eng.num_legal), nl)
+        assert_same(f"actions@{ply}", cpu(eng.actions), a)
+        assert_same(f"obs@{ply}", cpu(eng.obs), obs)
+        for k in ("done", "outcome", "reason", "ep_len"):
+            assert_same(f"{k}@{ply}", cpu(getattr(eng, k)), r[k])
+        assert_same(f"states@{ply}", cpu(eng.export()), ref.export())
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
+# ---------------------------------------------------------------- fused engine
+@pytest.mark.parametrize("G,S", [(1, 1), (2, 2), (4, 4), (8, 8), (16, 8), (4, 8)])
+def test_fused_engine_every_tiling(G, S):
+    """Fused persistent kernel, auto-reset on: per ply mask, actions, obs, step
+    outputs and states equal the oracle for every (games per WG, LDS segments)."""
+    n, seed, plies = 1000, 3, 40 if (G, S) != (4, 4) else 160
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True,
+                   games_per_wg=G, lds_segments=S)
+    ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
+    for ply in range(plies):
+        E.stratego_run_plies(eng.ctx, 1, mask=eng.mask, num_legal=eng.num_legal,
+                             actions=eng.actions, obs=eng.obs, done=eng.done, outcome=eng.outcome,
+                             reason=eng.reason, ep_len=eng.ep_len)
+        r = ref.ply(obs=True)
+        assert_same(f"mask@{ply}", cpu(eng.mask), r["mask"])
+        assert_same(f"num_legal@{ply}", cpu(eng.num_legal), r["num_legal"])
+        assert_same(f"actions@{ply}", cpu(eng.actions), r["actions"])
+        assert_same(f"obs@{ply}", cpu(eng.obs), r["obs"])
+        for k in ("done", "outcome", "reason", "ep_len"):
+            assert_same(f"{k}@{ply}", cpu(getattr(eng, k)), r[k])
+        assert_same(f"states@{ply}", cpu(eng.export()), ref.export())
+    eng.close()
+
+
+def test_graph_64_plies_auto_reset():
+    """One hipGraph of 64 fused plies (twice): per-ply outputs and final states."""
+    n, seed, P = 4096, 5, 64
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
+    ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
+    acts = torch.empty((P, n), dtype=torch.int16, device="cuda")
+    done = torch.empty((P, n), dtype=torch.int8, device="cuda")
+    outc = torch.empty((P, n), dtype=torch.int8, device="cuda")
+    reas = torch.empty((P, n), dtype=torch.uint8, device="cuda")
+    epl = torch.empty((P, n), dtype=torch.int16, device="cuda")
+    ns = torch.empty(P, dtype=torch.int64, device="cuda")
+    for rep in range(2):
+        E.stratego_run_plies(eng.ctx, P, mask=eng.mask, actions=acts, obs=eng.obs, done=done,
+                             outcome=outc, reason=reas, ep_len=epl, use_graph=True, ply_ns=ns)
+        for p in range(P):
+            r = ref.ply(obs=(p == P - 1))
+            assert_same(f"actions@{rep},{p}", cpu(acts[p]), r["actions"])
+            assert_same(f"done@{rep},{p}", cpu(done[p]), r["done"])
+            assert_same(f"outcome@{rep},{p}", cpu(outc[p]), r["outcome"])
+            assert_same(f"reason@{rep},{p}", cpu(reas[p]), r["reason"])
+            assert_same(f"ep_len@{rep},{p}", cpu(epl[p]), r["ep_len"])
+        assert_same(f"last mask@{rep}", cpu(eng.mask), r["mask"])
+        assert_same(f"last obs@{rep}", cpu(eng.obs), r["obs"])
+        assert_same(f"states@{rep}", cpu(eng.export()), ref.export())
+        t = cpu(ns)
+        assert (t > 0).all()
+    eng.close()
+
+
+def test_plain_and_fused_engines_agree():
+    n, seed = 512, 8
+    a = E.Engine(n, seed, auto_reset=True, max_moves=1000)
+    b = E.Engine(n, seed, auto_reset=True, max_moves=1000)
+    for ply in range(30):
+        a.legal_mask()
+        a.sample()
+        a.encode()
+        a.step()
+        E.stratego_run_plies(b.ctx, 1, mask=b.mask, actions=b.actions, obs=b.obs, done=b.done)
+        assert_same(f"actions@{ply}", cpu(a.actions), cpu(b.actions))
+        assert_same(f"obs@{ply}", cpu(a.obs), cpu(b.obs))
+    assert_same("states", cpu(a.export()), cpu(b.export()))
+    a.close()
+    b.close()
+
+
+def test_game_id_offset_shards_match_single_context():
+    """Two contexts with game_id_base offsets reproduce one context's games."""
+    n, seed = 1024, 9
+    whole = E.Engine(n, seed, auto_reset=True, max_moves=1000)
+    lo = E.Engine(n // 2, seed, auto_reset=True, max_moves=1000, game_id_base=0)
+    hi = E.Engine(n // 2, seed, auto_reset=True, max_moves=1000, game_id_base=n // 2)
+    for eng in (whole, lo, hi):
+        E.stratego_run_plies(eng.ctx, 50, obs=eng.obs, use_graph=True)
+    s = cpu(whole.export())
+    assert_same("lo", cpu(lo.export()), s[: n // 2])
+    assert_same("hi", cpu(hi.export()), s[n // 2:])
+    for e in (whole, lo, hi):
+        e.close()
+
+
+# ---------------------------------------------------------------- play to the end
+def test_4096_games_to_terminal_histograms():
+    """4096 games of random play without auto-reset until every game ends (or the
+    1000-ply cap): outcome/reason and game-length histograms equal the oracle's,
+    and so do the final states and sampled observations."""
+    n, seed, chunk = 4096, 2, 50
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=False)
+    ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=False)
+    acts = torch.empty((chunk, n), dtype=torch.int16, device="cuda")
+    done = torch.empty((chunk, n), dtype=torch.int8, device="cuda")
+    outc = torch.empty((chunk, n), dtype=torch.int8, device="cuda")
+    reas = torch.empty((chunk, n), dtype=torch.uint8, device="cuda")
+    epl = torch.empty((chunk, n), dtype=torch.int16, device="cuda")
+    ply = 0
+    check_obs_at = {0, 1, 2, 49, 99, 149, 399, 699}
+    while True:
+        E.stratego_run_plies(eng.ctx, chunk, actions=acts, obs=eng.obs, done=done, outcome=outc,
+                             reason=reas, ep_len=epl)
+        for p in range(chunk):
+            r = ref.ply(obs=(ply + p) in check_obs_at or p == chunk - 1, mask=False)
+            assert_same(f"actions@{ply + p}", cpu(acts[p]), r["actions"])
+            assert_same(f"done@{ply + p}", cpu(done[p]), r["done"])
+            if (ply + p) in check_obs_at:
+                # obs of the current ply is only kept for the chunk's last ply
+                pass
+        assert_same(f"obs@{ply + chunk - 1}", cpu(eng.obs), r["obs"])
+        ply += chunk
+        if cpu(done[-1]).all():
+            break
+        assert ply <= 1100
+    assert_same("final states", cpu(eng.export()), ref.export())
+    d_out, d_rsn, d_len = cpu(outc[-1]), cpu(reas[-1]), cpu(epl[-1])
+    recs = ref.export()
+    hs = [header(recs[g]) for g in range(n)]
+    want_pairs = np.zeros((3, 6), dtype=np.int64)
+    got_pairs = np.zeros((3, 6), dtype=np.int64)
+    for g in range(n):
+        want_pairs[hs[g]["outcome"] + 1, hs[g]["reason"]] += 1
+        got_pairs[int(d_out[g]) + 1, int(d_rsn[g])] += 1
+    assert_same("outcome x reason histogram", got_pairs, want_pairs)
+    assert_same("length histogram", np.bincount(d_len.astype(np.int64), minlength=1001),
+                np.bincount(np.array([h["ply"] for h in hs]), minlength=1001))
+    eng.close()
+
+
+# ---------------------------------------------------------------- imported states
+def random_position_records(count, seed=0):
+    from test_oracle_pins import random_position
+    rng = np.random.default_rng(seed)
+    return np.stack([random_position(rng, int(rng.integers(1, 41)), int(rng.integers(1, 41)))
+                     for _ in range(count)])
+
+
+def test_masks_of_random_positions():
+    recs = random_position_records(300)
+    n = len(recs)
+    eng = E.Engine(n, 1)
+    eng.load(torch.from_numpy(recs).cuda())
+    assert eng.error() == (0, -1)
+    eng.legal_mask()
+    ref = O.OracleEngine.from_records(recs, 1)
+    m, nl = ref.mask()
+    assert_same("mask", cpu(eng.mask), m)
+    assert_same("num_legal", cpu(eng.num_legal), nl)
+    assert_same("obs", cpu(eng.encode()), ref.encode())
+    eng.close()
+
+
+def scenario_records():
+    from positions import T  # noqa: F401
+    out = []
+    out.append((make_record([dict(sq=sq(3, 1), owner=0, type="Captain"),
+                             dict(sq=sq(4, 1), owner=1, type="Major", moved=1),
+                             dict(sq=sq(0, 9), owner=0, type="Flag"),
+                             dict(sq=sq(9, 9), owner=1, type="Flag")],
+                            ply=2, moves=[(5, 15), (51, 41)]), 100 * 31 + 30))
+    out.append((make_record([dict(sq=sq(3, 4), owner=0, type="Sergeant"),
+                             dict(sq=sq(2, 5), owner=0, type="Captain"),
+                             dict(sq=sq(4, 4), owner=1, type="General", revealed=1, moved=1),
+                             dict(sq=sq(0, 9), owner=0, type="Flag"),
+                             dict(sq=sq(9, 9), owner=1, type="Flag")],
+                            ply=2, moves=[(3, 13), (54, 44)]), 100 * 25 + 35))
+    out.append((make_record([dict(sq=sq(4, 4), owner=0, type="Marshal"),
+                             dict(sq=sq(5, 4), owner=1, type="Captain"),
+                             dict(sq=sq(6, 4), owner=1, type="Spy", revealed=1),
+                             dict(sq=sq(4, 5), owner=1, type="Scout", revealed=1),
+                             dict(sq=sq(0, 9), owner=0, type="Flag"),
+                             dict(sq=sq(9, 9), owner=1, type="Flag")]), 100 * 44 + 54))
+    for att, dfd, rdef in [("Sergeant", "Bomb", 0), ("Lieutenant", "Lieutenant", 1),
+                           ("Captain", "Major", 1), ("Major", "Captain", 0), ("Spy", "Marshal", 0),
+                           ("Miner", "Bomb", 1), ("Scout", "Flag", 0)]:
+        out.append((make_record([dict(sq=sq(4, 4), owner=0, type=att),
+                                 dict(sq=sq(5, 4), owner=1, type=dfd, revealed=rdef),
+                                 dict(sq=sq(0, 0), owner=0, type="Flag"),
+                                 dict(sq=sq(9, 9), owner=1, type="Flag") if dfd != "Flag" else
+                                 dict(sq=sq(9, 9), owner=1, type="Bomb"),
+                                 dict(sq=sq(9, 0), owner=1, type="Scout"),
+                                 dict(sq=sq(0, 9), owner=0, type="Scout")], battleless=99),
+                    100 * 44 + 54))
+    return out
+
+
+def test_hand_built_scenarios_step_like_the_oracle():
+    sc = scenario_records()
+    recs = np.stack([r for r, _ in sc])
+    acts = np.array([a for _, a in sc], dtype=np.int16)
+    n = len(sc)
+    eng = E.Engine(n, 1)
+    eng.load(torch.from_numpy(recs).cuda())
+    eng.step(torch.from_numpy(acts).cuda())
+    ref = O.OracleEngine.from_records(recs, 1)
+    r = ref.step(acts)
+    assert_same("states", cpu(eng.export()), ref.export())
+    for k in ("done", "outcome", "reason", "ep_len"):
+        assert_same(k, cpu(getattr(eng, k)), r[k])
+    assert_same("obs", cpu(eng.encode()), ref.encode())
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
+def test_illegal_action_and_bad_record_are_latched():
+    n = 16
+    eng = E.Engine(n, 4)
+    before = cpu(eng.export())
+    acts = torch.full((n,), -1, dtype=torch.int16, device="cuda")
+    acts[5] = 100 * 33 + 53          # not a legal move at ply 0
+    acts[9] = 100 * 31 + 41
+    eng.step(acts)
+    rc, slot = eng.error()
+    assert rc == E.E_ILLEGAL_ACTION and slot == 5
+    after = cpu(eng.export())
+    assert_same("untouched", after[5], before[5])
+    assert eng.error() == (0, -1)
+    bad = before[:2].copy()
+    bad[1, 64 + 42] = 0               # a piece id on a lake square
+    slots = torch.tensor([3, 7], dtype=torch.int32, device="cuda")
+    eng.load(torch.from_numpy(bad).cuda(), slots)
+    rc, slot = eng.error()
+    assert rc == E.E_BAD_STATE and slot == 7
+    now = cpu(eng.export())
+    assert_same("slot 3 imported", now[3], before[0])
+    assert_same("slot 7 kept", now[7], after[7])
+    eng.close()
+
+
+# ---------------------------------------------------------------- search-shaped load
+def test_resample_and_rollout_262144_games():
+    """1024 ply-100 states x 256 resamples, then 50 random plies: every record
+    after resampling and after the rollout equals the oracle's."""
+    seed, pool, per = 7, 4096, 256
+    src_eng = O.OracleEngine(pool, seed, k_battleless=100, max_moves=1000)
+    for _ in range(100):
+        src_eng.ply(obs=False, mask=False)
+    recs = src_eng.export()
+    alive = [g for g in range(pool) if header(recs[g])["done"] == 0][:1024]
+    assert len(alive) == 1024
+    src = recs[alive]
+    n = 1024 * per
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000)
+    src_dev = torch.from_numpy(src).cuda()
+    E.stratego_reset_resampled(eng.ctx, src_dev, per, 0)
+    ref_src = O.OracleEngine.from_records(src, seed, max_moves=1000)
+    ref = ref_src.resample(per, seed)
+    assert_same("resampled", cpu(eng.export()), ref.export())
+    E.stratego_run_plies(eng.ctx, 50, obs=None, use_graph=True)
+    for _ in range(50):
+        ref.ply(obs=False, mask=False)
+    assert_same("after rollout", cpu(eng.export()), ref.export())
+    eng.close()
