@@ -1,0 +1,238 @@
+"""Benchmark of the batched Stratego engine on one MI355X.
+
+Metric: game steps per second at 65,536 games, where one game step is a legal
+mask of the player to move + a uniform Philox sample + the step (battle,
+terminal and draw checks, auto-reset) + the uint8 observation encoding
+[2, 488, 10, 10] of both players.  The timed engine is the fused persistent
+kernel, one launch per ply, replayed from hipGraphs of 64 plies.  Inputs are
+synthetic: uniform random setups from the seed and uniform random legal play.
+
+Prints one JSON line.  Also reports per-ply p50/p99 latency (device
+timestamps), the HBM roofline fraction of the fused ply kernel, the plain
+per-call engine at the same size, the autotuner table and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+GAMES = 65536
+GRAPH_PLIES = 64
+K_BATTLELESS = 100
+MAX_MOVES = 1000
+SEED = 1
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of one game step of the fused ply: obs 97600 written,
+# mask 1256 written, num_legal 2, action 2, done/outcome/reason/ep_len 5,
+# state record 1536 read + 1536 written
+BYTES_PER_GAME_STEP = 97600 + 1256 + 2 + 2 + 5 + 2 * 1536
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def traffic_from_profile():
+    """HBM bytes per launch measured by rocprofv3 counters for the current
+    kernel source, or None when no such measurement exists."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fused_ply_65536_traffic.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("device.h", "engine.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2511_07312_amd", "csrc", f), "rb").read())
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(seconds=12.0):
+    """The CPU oracle on the host cores, same workload definition (fused ply
+    with both observations, auto-reset) on a bounded sample of games."""
+    import numpy as np
+    import oracle
+    n = 4096
+    ref = oracle.OracleEngine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True)
+    for _ in range(64):                      # advance past the opening (no encode)
+        ref.ply(obs=False, mask=False)
+    plies = 0
+    t0 = time.perf_counter()
+    while True:
+        ref.ply(obs=True)
+        plies += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or plies >= 20000:
+            break
+    return dict(value=n * plies / el, unit="game steps/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"games 0..{n - 1} of the same seed, {plies} fused plies each (mask, sample, "
+                       f"encode both players, step, auto-reset) after 64 unencoded plies; "
+                       f"{el:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=640, help="timed plies (multiple of 64)")
+    ap.add_argument("--warmup", type=int, default=1024, help="untimed plies before timing")
+    ap.add_argument("--games", type=int, default=GAMES)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tiling", default=None,
+                    help="G,S: use this games-per-WG / LDS-segment tiling instead of autotuning")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the engine shards games across GPUs with no "
+              "exchange step, so multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_07312_amd import engine as E
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = args.games
+    steps = max(GRAPH_PLIES, (args.steps // GRAPH_PLIES) * GRAPH_PLIES)
+    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True)
+    P = GRAPH_PLIES
+    acts = torch.empty((P, n), dtype=torch.int16, device="cuda")
+    done = torch.empty((P, n), dtype=torch.int8, device="cuda")
+    outc = torch.empty((P, n), dtype=torch.int8, device="cuda")
+    reas = torch.empty((P, n), dtype=torch.uint8, device="cuda")
+    epl = torch.empty((P, n), dtype=torch.int16, device="cuda")
+    ply_ns = torch.empty(P, dtype=torch.int64, device="cuda")
+    obs = eng.obs
+
+    def graph_plies(timed):
+        E.stratego_run_plies(eng.ctx, P, mask=eng.mask, num_legal=eng.num_legal, actions=acts,
+                             obs=obs, done=done, outcome=outc, reason=reas, ep_len=epl,
+                             use_graph=True, ply_ns=ply_ns if timed else None)
+
+    # warm-up: desynchronise the games (boards reset independently)
+    for _ in range(max(1, args.warmup // P)):
+        graph_plies(False)
+    torch.cuda.synchronize()
+    print(f"[bench] warm-up {args.warmup} plies done", file=sys.stderr, flush=True)
+
+    tune = []
+    if args.tiling:
+        g, s_ = (int(x) for x in args.tiling.split(","))
+        E.stratego_set_tiling(eng.ctx, g, s_)
+    elif not args.no_tune:
+        tune = E.stratego_autotune(eng.ctx, obs, eng.mask, plies=8)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
+    G, S = E.stratego_get_tiling(eng.ctx)
+    graph_plies(True)                       # capture the graph for the chosen tiling
+    torch.cuda.synchronize()
+
+    # timed region
+    lat = []
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    per_launch = []
+    for _ in range(steps // P):
+        graph_plies(True)
+        per_launch.append(ply_ns.clone())
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    for t in per_launch:
+        lat += [x / 1e6 for x in t.cpu().tolist()]
+    assert eng.error() == (0, -1)
+    ms_per_step = gpu_ms / steps
+    value = n * steps / (gpu_ms / 1e3)
+    kernel_ms = sum(lat) / len(lat)          # mean device duration of one ply kernel
+    achieved = BYTES_PER_GAME_STEP * n / (ms_per_step / 1e3) / 1e9
+    traffic = traffic_from_profile()
+    print(f"[bench] timed {steps} plies: {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms)",
+          file=sys.stderr, flush=True)
+
+    plain = None
+    if not args.no_plain:
+        pl = []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for i in range(24):
+            e0.record(stream)
+            eng.legal_mask()
+            eng.sample()
+            eng.encode()
+            eng.step()
+            e1.record(stream)
+            e1.synchronize()
+            if i >= 4:
+                pl.append(e0.elapsed_time(e1))
+        plain = dict(value=n / (sum(pl) / len(pl) / 1e3), unit="game steps/s",
+                     p50_ms=percentile(pl, 0.5), p99_ms=percentile(pl, 0.99), plies=len(pl),
+                     engine="plain per-call kernels (legal_mask, sample, encode_obs, step)")
+        print(f"[bench] plain engine: {plain}", file=sys.stderr, flush=True)
+        assert eng.error() == (0, -1)
+    eng.close()
+    del obs, eng
+    torch.cuda.empty_cache()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+
+    out = {
+        "metric": "game steps/sec (mask+step+encode) at 65536 games; p50/p99 step latency",
+        "value": value,
+        "unit": "game steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic: uniform random setups and uniform random legal play (Philox4x32-10)",
+        "config": {
+            "workload": f"{n} games, fused persistent ply kernel (mask, sample, encode both "
+                        f"players [2,488,10,10] uint8, step, auto-reset), hipGraph of {P} plies",
+            "games": n, "plies_per_graph": P, "k_battleless": K_BATTLELESS,
+            "max_moves": MAX_MOVES, "seed": SEED, "games_per_wg": G, "lds_segments": S,
+            "parallelism": "single GPU",
+        },
+        "p50_ms": percentile(lat, 0.5),
+        "p99_ms": percentile(lat, 0.99),
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_ply<15> (fused ply)", "bytes_per_game_step": BYTES_PER_GAME_STEP,
+            "kernel_ms_device_timestamps": kernel_ms,
+        },
+        "plain_engine": plain,
+        "autotune": [dict(games_per_wg=g, lds_segments=s, us_per_ply=u) for g, s, u in tune],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -69,6 +69,7 @@ def lib():
         L.orc_fnv1a64.argtypes = [P, ctypes.c_size_t]
         L.orc_fnv1a64.restype = ctypes.c_uint64
         L.orc_board_string.argtypes = [P, ctypes.c_char_p]
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -94,6 +95,10 @@ def setup_types(seed, game_id, episode, player):
     out = np.zeros(40, dtype=np.int32)
     lib().orc_setup_types(seed, game_id, episode, player, _p(out))
     return out
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def fnv1a64(buf):

@@ -991,6 +991,14 @@ void orc_batch_ply(orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int1
     }
 }
 
+/* Threads the batch entry points use (OpenMP), for reporting. */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_num_threads(void) { return 1; }
+#endif
+
 /* Single-game helpers for tests. */
 int orc_legal_list(const orc_state* st, int player, unsigned char* legal10000) {
     return legal_actions(st, player, legal10000);
