@@ -90,6 +90,66 @@ def cpu_baseline(seconds=12.0):
                        f"{el:.1f} s wall")
 
 
+def serving_bench(E, torch, n_requests=240, seed=4):
+    """Continuous-batching serving: Poisson arrivals, half step requests (one
+    ply with both observations) and half k-ply rollouts (k uniform in 1..128),
+    batch sizes floor(exp(U(0, ln 16384))), start states drawn from games of
+    random play without auto-reset.  Measures the saturated rate, then p50/p99
+    latency and throughput at 0.3, 0.6 and 0.9 of it."""
+    import math
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    # start-state pool from 4096 games of random play (no auto-reset)
+    src = E.Engine(4096, 2, K_BATTLELESS, MAX_MOVES, auto_reset=False)
+    pool = []
+    for _ in range(5):
+        E.stratego_run_plies(src.ctx, 30, obs=None, use_graph=True)
+        pool.append(src.export())
+    pool = torch.cat(pool)
+    src.close()
+    kinds = rng.integers(0, 2, size=n_requests)
+    sizes = np.floor(np.exp(rng.uniform(0, math.log(16384), size=n_requests))).astype(int)
+    plies = np.where(kinds == 0, 1, rng.integers(1, 129, size=n_requests))
+    firsts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    total = int(sizes.sum())
+    rows = torch.from_numpy(rng.integers(0, pool.shape[0], size=total)).cuda()
+    inp = pool[rows].contiguous()
+    out = torch.empty_like(inp)
+    slots = 65536
+    eng = E.Engine(slots, 2, K_BATTLELESS, MAX_MOVES, auto_reset=False)
+    obs_pool = torch.empty((slots, 2, 488, 10, 10), dtype=torch.uint8, device="cuda")
+    gaps = rng.exponential(1.0, size=n_requests)
+
+    def run(rate):
+        arr = np.zeros(n_requests) if rate is None else np.cumsum(gaps) / rate
+        reqs = [(int(kinds[r]), int(plies[r]), int(sizes[r]), int(firsts[r]), float(arr[r]))
+                for r in range(n_requests)]
+        res, st = E.stratego_serve(eng.ctx, reqs, inp, out, obs_pool, obs_by_slot=True,
+                                   mem_budget_bytes=0, realtime=rate is not None)
+        lat = {0: [], 1: []}
+        for r, (a, d) in enumerate(res):
+            lat[int(kinds[r])].append((d - arr[r]) * 1e3)
+        return st, lat
+
+    st, _ = run(None)
+    sat = st["game_steps"] / st["wall_s"]
+    mean_work = float((sizes * plies).mean())
+    out_rates = []
+    for f in (0.3, 0.6, 0.9):
+        rate = f * sat / mean_work            # requests per second
+        st, lat = run(rate)
+        out_rates.append(dict(
+            load=f, requests_per_s=rate, throughput=st["game_steps"] / st["wall_s"],
+            step_p50_ms=percentile(lat[0], 0.5), step_p99_ms=percentile(lat[0], 0.99),
+            rollout_p50_ms=percentile(lat[1], 0.5), rollout_p99_ms=percentile(lat[1], 0.99),
+            iterations=st["iterations"], peak_active_games=st["peak_active_games"]))
+        print(f"[bench] serving at {f:.1f}x: {out_rates[-1]}", file=sys.stderr, flush=True)
+    assert eng.error() == (0, -1)
+    eng.close()
+    return dict(unit="game steps/s", saturated=sat, requests=n_requests, games=total,
+                pool_slots=slots, rates=out_rates)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +159,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--tiling", default=None,
                     help="G,S: use this games-per-WG / LDS-segment tiling instead of autotuning")
     args = ap.parse_args()
@@ -128,6 +191,14 @@ def main():
         E.stratego_run_plies(eng.ctx, P, mask=eng.mask, num_legal=eng.num_legal, actions=acts,
                              obs=obs, done=done, outcome=outc, reason=reas, ep_len=epl,
                              use_graph=True, ply_ns=ply_ns if timed else None)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # warm-up: desynchronise the games (boards reset independently)
     for _ in range(max(1, args.warmup // P)):
@@ -196,6 +267,8 @@ def main():
     eng.close()
     del obs, eng
     torch.cuda.empty_cache()
+    serving = None if args.no_serving else serving_bench(E, torch)
+    torch.cuda.empty_cache()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -228,6 +301,7 @@ def main():
             "kernel_ms_device_timestamps": kernel_ms,
         },
         "plain_engine": plain,
+        "serving": serving,
         "autotune": [dict(games_per_wg=g, lds_segments=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }

@@ -150,6 +150,52 @@ int stratego_run_plies_slots(stratego_ctx* ctx, const int32_t* slots_dev, int32_
 int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int32_t nsrc,
                              int32_t per, uint32_t game_id_base);
 
+/* Serving (continuous batching).  A request asks for `plies` fused plies of
+ * num_games games whose canonical records sit at rows [first, first +
+ * num_games) of in_states_dev.  Kinds: STRATEGO_REQ_STEP (plies must be 1; the
+ * observations of both players of the input states are written to obs_out_dev
+ * at rows first + j, or at the game's pool slot when obs_by_slot = 1) and
+ * STRATEGO_REQ_ROLLOUT (no observations).  The context's N slots are the
+ * device-resident pool.  Requests are admitted first come first served, as
+ * soon as they have arrived (realtime = 1: at arrival_s seconds after the call
+ * starts; realtime = 0: all at once) and both enough free slots and enough of
+ * the memory budget remain (a game reserves 1536 bytes, plus 97600 for step
+ * requests); mem_budget_bytes <= 0 uses the device's free memory at the start
+ * of the call.  Every iteration runs one fused ply over all admitted games, so
+ * requests that arrive while others run join them on the device; a request
+ * leaves after its last ply, when its final records are copied to rows
+ * [first, first + num_games) of out_states_dev.  results[r] receives admission
+ * and completion times.  Each game's result depends only on its record, so it
+ * is the same alone and in any mix.  The error word latches E_BAD_STATE for a
+ * malformed input record (that game then runs from whatever its slot held).
+ * Synchronises the stream.  Errors: E_INVAL (bad request, a request that can
+ * never fit, step requests without obs_out_dev), E_HIP. */
+#define STRATEGO_REQ_STEP 0
+#define STRATEGO_REQ_ROLLOUT 1
+typedef struct {
+  int32_t kind;
+  int32_t plies;
+  int32_t num_games;
+  int32_t first;
+  double arrival_s;
+} stratego_request;
+typedef struct {
+  double admit_s;
+  double done_s;
+} stratego_request_result;
+typedef struct {
+  double wall_s;
+  int64_t game_steps;
+  int32_t iterations;
+  int32_t peak_active_games;
+  int64_t peak_reserved_bytes;
+  int64_t budget_bytes;
+} stratego_serve_stats;
+int stratego_serve(stratego_ctx* ctx, const stratego_request* reqs, int32_t nreq,
+                   const void* in_states_dev, void* out_states_dev, uint8_t* obs_out_dev,
+                   int32_t obs_by_slot, int64_t mem_budget_bytes, int32_t realtime,
+                   stratego_request_result* results, stratego_serve_stats* stats);
+
 /* Time the fused engine for every (games_per_wg, lds_segments) pair that fits
  * the device, plies plies each, restoring the game states afterwards, and
  * adopt the fastest.  report (may be NULL) receives up to max_entries rows of

@@ -730,16 +730,21 @@ __device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rul
                                 const SegWriter& W) {
   const int lane = lane_id();
   const int ply = (int)hdr_u32(R, kOffPly);
+  // 41-42: fractions of the move budget and of the k-move budget, on every square
+  if (W.overlaps(41, 43)) {
+    const uint8_t v41 = (uint8_t)quant255((uint32_t)ply, (uint32_t)rules.max_moves);
+    const uint8_t v42 = (uint8_t)quant255(hdr_u32(R, kOffBattleless), (uint32_t)rules.k_battleless);
+    for (int f = lane; f < kSquares; f += 64) {
+      W.put(41, f, v41);
+      W.put(42, f, v42);
+    }
+  }
   // squares
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
     int s = lane + 64 * h;
     if (s >= kSquares) break;
     const int f = o == 0 ? s : 99 - s;
-    if (W.overlaps(41, 43)) {
-      W.put(41, f, (uint8_t)quant255((uint32_t)ply, (uint32_t)rules.max_moves));
-      W.put(42, f, (uint8_t)quant255(hdr_u32(R, kOffBattleless), (uint32_t)rules.k_battleless));
-    }
     const int id = board_at(R, s);
     if (id == kLake) continue;
     if (id == kEmpty) {
@@ -821,30 +826,56 @@ __device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rul
   }
 }
 
-// Encode both observers of the game staged in R into obs (global, 97600 bytes),
-// building each segment of channels in the LDS image and streaming it out with
-// 16-byte stores.
+// The LDS image region of a wave's slab is kept all-zero between uses: it is
+// cleared once when a kernel starts, every segment's copy-out clears what it
+// read, and the legal-move phase clears the destination sets it parked there.
+__device__ __forceinline__ void clear_lds(uint8_t* p, int bytes) {
+  u32x4* q = reinterpret_cast<u32x4*>(p);
+  const u32x4 z = {0u, 0u, 0u, 0u};
+  for (int k = lane_id(); k < bytes / 16; k += 64) q[k] = z;
+  wave_sync();
+}
+
+// Bytes of the 101 destination sets legal_mask_words parks in the image.
+constexpr int kDestSetBytes = 101 * 16;
+
+// Encode both observers of the game staged in R into obs (global, 97600 bytes).
+// Per segment of channels: scatter the non-zero bytes into the (zero) LDS
+// image, then stream it to HBM with non-temporal 16-byte stores, four loads in
+// flight per lane, clearing the image behind the reads.
 __device__ void encode_game(const uint8_t* R, uint8_t* slab, const Rules& rules, int segments,
                             uint8_t* obs) {
   const int lane = lane_id();
   const int segc = seg_channels_for(segments);
   uint8_t* img = slab + kSlabImage;
-  uint4* img4 = reinterpret_cast<uint4*>(img);
+  u32x4* im = reinterpret_cast<u32x4*>(img);
+  const u32x4 z = {0u, 0u, 0u, 0u};
 #pragma unroll 1
   for (int o = 0; o < 2; ++o) {
 #pragma unroll 1
     for (int c_lo = 0; c_lo < kChannels; c_lo += segc) {
       const int c_hi = c_lo + segc < kChannels ? c_lo + segc : kChannels;
       const int chunks = (c_hi - c_lo) * 100 / 16;
-      for (int k = lane; k < chunks; k += 64) img4[k] = make_uint4(0, 0, 0, 0);
-      wave_sync();
       SegWriter W{img, c_lo, c_hi};
       scatter_segment(R, slab, rules, o, W);
       wave_sync();
-      uint4* dst = reinterpret_cast<uint4*>(obs + o * kObsPerObserver + c_lo * 100);
-      for (int k = lane; k < chunks; k += 64) {
-        u32x4 v = reinterpret_cast<const u32x4*>(img4)[k];
-        __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(dst) + k);
+      u32x4* dst = reinterpret_cast<u32x4*>(obs + o * kObsPerObserver + c_lo * 100);
+      int k = lane;
+      for (; k + 192 < chunks; k += 256) {
+        u32x4 v0 = im[k], v1 = im[k + 64], v2 = im[k + 128], v3 = im[k + 192];
+        im[k] = z;
+        im[k + 64] = z;
+        im[k + 128] = z;
+        im[k + 192] = z;
+        __builtin_nontemporal_store(v0, dst + k);
+        __builtin_nontemporal_store(v1, dst + k + 64);
+        __builtin_nontemporal_store(v2, dst + k + 128);
+        __builtin_nontemporal_store(v3, dst + k + 192);
+      }
+      for (; k < chunks; k += 64) {
+        u32x4 v = im[k];
+        im[k] = z;
+        __builtin_nontemporal_store(v, dst + k);
       }
       wave_sync();
     }

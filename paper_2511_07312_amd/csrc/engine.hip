@@ -7,10 +7,13 @@
 // per workgroup, plies optionally replayed from a captured hipGraph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "stratego.h"
@@ -30,6 +33,7 @@ struct PlyArgs {
   int32_t n;
   int32_t total;      // games in the context (slot range)
   int32_t out_base;   // index of this ply's row in [nplies][n] outputs
+  const int32_t* out_index;   // output row of game i (NULL: i)
   uint64_t* mask;
   int16_t* num_legal;
   const int16_t* actions_in;
@@ -53,6 +57,8 @@ __global__ void __launch_bounds__(256) k_ply(PlyArgs a) {
   uint8_t* slab = smem + wave * slab_bytes_for(a.segments);
   uint8_t* R = slab;
   if (a.ts && threadIdx.x == 0) atomicMin(&a.ts[0], (unsigned long long)wall_clock64());
+  const bool encode = (MODE & kDoEncode) && a.obs;
+  if (encode) clear_lds(slab + kSlabImage, 100 * seg_channels_for(a.segments));
   const int G = a.games_per_tile;
   const int ntiles = (a.n + G - 1) / G;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -65,40 +71,40 @@ __global__ void __launch_bounds__(256) k_ply(PlyArgs a) {
         continue;
       }
       uint8_t* gstate = a.states + (size_t)slot * kRecordBytes;
+      const int oi = a.out_index ? a.out_index[i] : i;
       load_record(R, gstate);
       int action = -1;
       if (MODE & kDoMask) {
         uint64_t w[3];
         const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
         if (a.mask) {
-          uint64_t* m = a.mask + (size_t)i * kMaskWords;
+          uint64_t* m = a.mask + (size_t)oi * kMaskWords;
 #pragma unroll
           for (int g = 0; g < 3; ++g)
             if (lane + 64 * g < kMaskWords) m[lane + 64 * g] = w[g];
         }
-        if (a.num_legal && lane == 0) a.num_legal[i] = (int16_t)n;
+        if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
         if (MODE & kDoSample) {
           action = sample_from_words(w, n, a.rules.seed, hdr_u32(R, kOffGameId),
                                      hdr_u32(R, kOffPly), hdr_u32(R, kOffEpisode));
-          if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + i] = (int16_t)action;
+          if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
         }
         wave_sync();
+        if (encode) clear_lds(slab + kSlabImage, kDestSetBytes);
       }
       if (MODE & kStepFromInput) action = a.actions_in[i];
-      if (MODE & kDoEncode) {
-        if (a.obs) {
-          compute_probq(R, slab);
-          encode_game(R, slab, a.rules, a.segments, a.obs + (size_t)i * kObsPerGame);
-        }
+      if (encode) {
+        compute_probq(R, slab);
+        encode_game(R, slab, a.rules, a.segments, a.obs + (size_t)oi * kObsPerGame);
       }
       if (MODE & kDoStep) {
         StepOut o = step_game(R, slab + kSlabScratch, a.rules, action);
         if (lane == 0) {
-          const size_t oi = (size_t)a.out_base + i;
-          if (a.done) a.done[oi] = (int8_t)o.done;
-          if (a.outcome) a.outcome[oi] = (int8_t)o.outcome;
-          if (a.reason) a.reason[oi] = (uint8_t)o.reason;
-          if (a.ep_len) a.ep_len[oi] = (int16_t)o.ep_len;
+          const size_t row = (size_t)a.out_base + oi;
+          if (a.done) a.done[row] = (int8_t)o.done;
+          if (a.outcome) a.outcome[row] = (int8_t)o.outcome;
+          if (a.reason) a.reason[row] = (uint8_t)o.reason;
+          if (a.ep_len) a.ep_len[row] = (int16_t)o.ep_len;
           if (o.illegal) atomicMin(&a.err[0], slot);
         }
         wave_sync();
@@ -189,6 +195,18 @@ __global__ void __launch_bounds__(256) k_resample(uint8_t* states, const uint8_t
   store_record(states + (size_t)k * kRecordBytes, slab);
 }
 
+// Copy the records of the listed slots to out (contiguous).
+__global__ void __launch_bounds__(256) k_gather(const uint8_t* states, const int32_t* slots, int32_t n,
+                                               uint8_t* out) {
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (i >= n) return;
+  const uint4* src = reinterpret_cast<const uint4*>(states + (size_t)slots[i] * kRecordBytes);
+  uint4* dst = reinterpret_cast<uint4*>(out + (size_t)i * kRecordBytes);
+  dst[lane] = src[lane];
+  if (lane < 32) dst[64 + lane] = src[64 + lane];
+}
+
 __global__ void k_ts_init(unsigned long long* ts, int32_t nplies) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nplies) {
@@ -228,6 +246,8 @@ struct stratego_ctx {
   uint8_t* backup;   // copy of the states while the autotuner runs
   int32_t* err;
   unsigned long long* ts;
+  int32_t* srv_dev;    // serving slot lists, 4 x N
+  int32_t* srv_host;   // pinned host staging of the same lists
   int64_t steps;
   int G, S;
   std::vector<GraphEntry> graphs;
@@ -388,6 +408,18 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
     delete c;
     return STRATEGO_E_HIP;
   }
+  const size_t lists = 4 * (size_t)cfg->num_games * sizeof(int32_t);
+  if (hipMalloc(&c->srv_dev, lists) != hipSuccess) {
+    c->srv_dev = nullptr;
+    c->srv_host = nullptr;
+    stratego_destroy(c);
+    return STRATEGO_E_NOMEM;
+  }
+  if (hipHostMalloc(&c->srv_host, lists, hipHostMallocDefault) != hipSuccess) {
+    c->srv_host = nullptr;
+    stratego_destroy(c);
+    return STRATEGO_E_NOMEM;
+  }
   // kernels whose dynamic LDS may exceed the default limit
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ply<kFused>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->max_lds);
@@ -539,6 +571,188 @@ int stratego_reset_resampled(stratego_ctx* c, const void* src, int32_t nsrc, int
   return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
 }
 
+int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, const void* in_states,
+                   void* out_states, uint8_t* obs_out, int32_t obs_by_slot, int64_t mem_budget,
+                   int32_t realtime, stratego_request_result* results, stratego_serve_stats* stats) {
+  if (!c || nreq < 0 || (nreq > 0 && (!reqs || !in_states || !out_states || !results)))
+    return STRATEGO_E_INVAL;
+  const int N = c->cfg.num_games;
+  bool any_step = false;
+  for (int r = 0; r < nreq; ++r) {
+    const stratego_request& q = reqs[r];
+    if ((q.kind != STRATEGO_REQ_STEP && q.kind != STRATEGO_REQ_ROLLOUT) || q.num_games < 1 ||
+        q.num_games > N || q.first < 0 || q.plies < 1 || q.plies > 32767 || !(q.arrival_s >= 0.0) ||
+        (q.kind == STRATEGO_REQ_STEP && q.plies != 1))
+      return STRATEGO_E_INVAL;
+    any_step |= q.kind == STRATEGO_REQ_STEP;
+  }
+  if (any_step && !obs_out) return STRATEGO_E_INVAL;
+  int64_t budget = mem_budget;
+  if (budget <= 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return STRATEGO_E_HIP;
+    budget = (int64_t)free_b;
+  }
+  auto bytes_of = [](const stratego_request& q) -> int64_t {
+    return (int64_t)q.num_games * (kRecordBytes + (q.kind == STRATEGO_REQ_STEP ? kObsPerGame : 0));
+  };
+  for (int r = 0; r < nreq; ++r)
+    if (bytes_of(reqs[r]) > budget) return STRATEGO_E_INVAL;   // could never be admitted
+
+  // admission in arrival order (first come, first served)
+  std::vector<int> order(nreq);
+  for (int r = 0; r < nreq; ++r) order[r] = r;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+  std::vector<int32_t> free_slots(N);
+  for (int i = 0; i < N; ++i) free_slots[i] = N - 1 - i;
+  struct Active { int req; int remaining; std::vector<int32_t> slots; };
+  std::vector<Active> active;
+  int32_t* h_adm = c->srv_host;
+  int32_t* h_step = c->srv_host + N;
+  int32_t* h_roll = c->srv_host + 2 * (size_t)N;
+  int32_t* h_oidx = c->srv_host + 3 * (size_t)N;
+  int32_t* d_adm = c->srv_dev;
+  int32_t* d_step = c->srv_dev + N;
+  int32_t* d_roll = c->srv_dev + 2 * (size_t)N;
+  int32_t* d_oidx = c->srv_dev + 3 * (size_t)N;
+  const uint8_t* in = reinterpret_cast<const uint8_t*>(in_states);
+  uint8_t* out = reinterpret_cast<uint8_t*>(out_states);
+  int64_t reserved = 0, game_steps = 0, peak_reserved = 0;
+  int next = 0, completed = 0, iterations = 0, peak_active = 0, active_games = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto now_s = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  while (completed < nreq) {
+    // 1. admit arrived requests while slots and memory allow
+    double t = now_s();
+    int nadm = 0;
+    std::vector<int> admitted;
+    while (next < nreq) {
+      const stratego_request& q = reqs[order[next]];
+      if (realtime && q.arrival_s > t) break;
+      if ((int)free_slots.size() < q.num_games || reserved + bytes_of(q) > budget) break;
+      Active a;
+      a.req = order[next];
+      a.remaining = q.plies;
+      a.slots.resize(q.num_games);
+      for (int j = 0; j < q.num_games; ++j) {
+        a.slots[j] = free_slots.back();
+        free_slots.pop_back();
+        h_adm[nadm + j] = a.slots[j];
+      }
+      admitted.push_back(nadm);
+      nadm += q.num_games;
+      reserved += bytes_of(q);
+      active_games += q.num_games;
+      results[a.req].admit_s = t;
+      active.push_back(std::move(a));
+      ++next;
+    }
+    peak_reserved = std::max(peak_reserved, reserved);
+    peak_active = std::max(peak_active, active_games);
+    if (active.empty()) {
+      if (next < nreq) {   // idle until the next arrival
+        const double wait = reqs[order[next]].arrival_s - now_s();
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 2e-4)));
+        continue;
+      }
+      break;
+    }
+    if (nadm > 0) {
+      if (hipMemcpyAsync(d_adm, h_adm, nadm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return STRATEGO_E_HIP;
+      const size_t first_new = active.size() - admitted.size();
+      for (size_t k = 0; k < admitted.size(); ++k) {
+        const Active& a = active[first_new + k];
+        const stratego_request& q = reqs[a.req];
+        hipLaunchKernelGGL(k_import, dim3(grid_for(q.num_games, 4)), dim3(256), 4 * kSlabImage, c->stream,
+                           c->states, d_adm + admitted[k], q.num_games, N, in + (size_t)q.first * kRecordBytes,
+                           c->err);
+      }
+    }
+    // 2. one fused ply for every active game: step requests with observations,
+    //    rollout requests without
+    int nstep = 0, nroll = 0;
+    std::vector<int> run_off(active.size());
+    for (size_t k = 0; k < active.size(); ++k) {
+      const Active& a = active[k];
+      const stratego_request& q = reqs[a.req];
+      if (q.kind == STRATEGO_REQ_STEP) {
+        run_off[k] = nstep;
+        for (int j = 0; j < q.num_games; ++j) {
+          h_step[nstep + j] = a.slots[j];
+          h_oidx[nstep + j] = obs_by_slot ? a.slots[j] : q.first + j;
+        }
+        nstep += q.num_games;
+      } else {
+        run_off[k] = nroll;
+        for (int j = 0; j < q.num_games; ++j) h_roll[nroll + j] = a.slots[j];
+        nroll += q.num_games;
+      }
+    }
+    if (nstep > 0 &&
+        (hipMemcpyAsync(d_step, h_step, nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+         hipMemcpyAsync(d_oidx, h_oidx, nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess))
+      return STRATEGO_E_HIP;
+    if (nroll > 0 &&
+        hipMemcpyAsync(d_roll, h_roll, nroll * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return STRATEGO_E_HIP;
+    if (nstep > 0) {
+      PlyArgs a = base_args(c);
+      a.slots = d_step;
+      a.n = nstep;
+      a.out_index = d_oidx;
+      a.obs = obs_out;
+      int rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
+      if (rc != STRATEGO_OK) return rc;
+    }
+    if (nroll > 0) {
+      PlyArgs a = base_args(c);
+      a.slots = d_roll;
+      a.n = nroll;
+      int rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
+      if (rc != STRATEGO_OK) return rc;
+    }
+    game_steps += nstep + nroll;
+    // 3. retire requests whose plies are done: copy their records out
+    std::vector<size_t> finished;
+    for (size_t k = 0; k < active.size(); ++k) {
+      Active& a = active[k];
+      if (--a.remaining > 0) continue;
+      const stratego_request& q = reqs[a.req];
+      const int32_t* list = (q.kind == STRATEGO_REQ_STEP ? d_step : d_roll) + run_off[k];
+      hipLaunchKernelGGL(k_gather, dim3(grid_for(q.num_games, 4)), dim3(256), 0, c->stream, c->states, list,
+                         q.num_games, out + (size_t)q.first * kRecordBytes);
+      finished.push_back(k);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return STRATEGO_E_HIP;
+    ++iterations;
+    t = now_s();
+    for (size_t f = finished.size(); f-- > 0;) {
+      Active& a = active[finished[f]];
+      const stratego_request& q = reqs[a.req];
+      results[a.req].done_s = t;
+      for (int32_t sl : a.slots) free_slots.push_back(sl);
+      reserved -= bytes_of(q);
+      active_games -= q.num_games;
+      ++completed;
+      active.erase(active.begin() + (long)finished[f]);
+    }
+  }
+  c->steps += game_steps;
+  if (stats) {
+    stats->wall_s = now_s();
+    stats->game_steps = game_steps;
+    stats->iterations = iterations;
+    stats->peak_active_games = peak_active;
+    stats->peak_reserved_bytes = peak_reserved;
+    stats->budget_bytes = budget;
+  }
+  return STRATEGO_OK;
+}
+
 int stratego_get_tiling(stratego_ctx* c, int32_t* G, int32_t* S) {
   if (!c) return STRATEGO_E_INVAL;
   if (G) *G = c->G;
@@ -639,6 +853,8 @@ int stratego_destroy(stratego_ctx* c) {
   for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
   c->graphs.clear();
   (void)hipStreamDestroy(c->capture_stream);
+  if (c->srv_dev) (void)hipFree(c->srv_dev);
+  if (c->srv_host) (void)hipHostFree(c->srv_host);
   (void)hipFree(c->states);
   (void)hipFree(c->backup);
   (void)hipFree(c->err);

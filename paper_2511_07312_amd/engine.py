@@ -29,8 +29,10 @@ FUNCTIONS = [
     "stratego_step", "stratego_encode_obs", "stratego_export_states", "stratego_run_plies",
     "stratego_run_plies_slots", "stratego_reset_resampled", "stratego_autotune",
     "stratego_get_tiling", "stratego_set_tiling", "stratego_get_error", "stratego_current_step",
-    "stratego_destroy", "stratego_strerror",
+    "stratego_destroy", "stratego_strerror", "stratego_serve",
 ]
+REQ_STEP = 0
+REQ_ROLLOUT = 1
 
 
 class StrategoConfig(ctypes.Structure):
@@ -44,6 +46,21 @@ class StrategoConfig(ctypes.Structure):
 class TuneEntry(ctypes.Structure):
     _fields_ = [("games_per_wg", ctypes.c_int32), ("lds_segments", ctypes.c_int32),
                 ("us_per_ply", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("plies", ctypes.c_int32), ("num_games", ctypes.c_int32),
+                ("first", ctypes.c_int32), ("arrival_s", ctypes.c_double)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("game_steps", ctypes.c_int64),
+                ("iterations", ctypes.c_int32), ("peak_active_games", ctypes.c_int32),
+                ("peak_reserved_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64)]
 
 
 class StrategoError(RuntimeError):
@@ -81,6 +98,8 @@ def load_library(path=LIB_PATH):
     L.stratego_get_error.argtypes = [P, ctypes.POINTER(I32)]
     L.stratego_current_step.argtypes = [P, ctypes.POINTER(I64)]
     L.stratego_destroy.argtypes = [P]
+    L.stratego_serve.argtypes = [P, ctypes.POINTER(Request), I32, P, P, P, I32, I64, I32,
+                                 ctypes.POINTER(RequestResult), ctypes.POINTER(ServeStats)]
     L.stratego_strerror.argtypes = [ctypes.c_int]
     L.stratego_strerror.restype = ctypes.c_char_p
     for f in FUNCTIONS:
@@ -219,6 +238,28 @@ def stratego_autotune(ctx, obs, mask, plies=3, max_entries=32):
                                             _ptr(mask, torch.int64, None, "mask"), int(plies), rep,
                                             max_entries, ctypes.byref(n)), "stratego_autotune")
     return [(rep[i].games_per_wg, rep[i].lds_segments, rep[i].us_per_ply) for i in range(n.value)]
+
+
+def stratego_serve(ctx, requests, in_states, out_states, obs_out=None, obs_by_slot=False,
+                   mem_budget_bytes=0, realtime=True):
+    """requests: sequence of (kind, plies, num_games, first, arrival_s).
+    Returns (list of (admit_s, done_s), stats dict)."""
+    nreq = len(requests)
+    reqs = (Request * max(nreq, 1))()
+    total = 0
+    for r, (kind, plies, b, first, arr) in enumerate(requests):
+        reqs[r] = Request(int(kind), int(plies), int(b), int(first), float(arr))
+        total = max(total, int(first) + int(b))
+    res = (RequestResult * max(nreq, 1))()
+    st = ServeStats()
+    obs_rows = None if obs_out is None or obs_by_slot else total * OBS_BYTES_PER_GAME
+    _check(load_library().stratego_serve(
+        ctx, reqs, nreq, _ptr(in_states, torch.uint8, total * RECORD_BYTES, "in_states"),
+        _ptr(out_states, torch.uint8, total * RECORD_BYTES, "out_states"),
+        _ptr(obs_out, torch.uint8, obs_rows, "obs_out"), int(bool(obs_by_slot)),
+        int(mem_budget_bytes), int(bool(realtime)), res, ctypes.byref(st)), "stratego_serve")
+    stats = {k: getattr(st, k) for k, _ in ServeStats._fields_}
+    return [(res[r].admit_s, res[r].done_s) for r in range(nreq)], stats
 
 
 def stratego_get_tiling(ctx):

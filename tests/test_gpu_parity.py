@@ -308,3 +308,64 @@ def test_resample_and_rollout_262144_games():
         ref.ply(obs=False, mask=False)
     assert_same("after rollout", cpu(eng.export()), ref.export())
     eng.close()
+
+
+# ---------------------------------------------------------------- serving
+def serving_inputs(total, seed=2):
+    """Start states drawn from games of random play without auto-reset (the
+    4096-game workload), taken at different plies."""
+    ref = O.OracleEngine(2048, seed, k_battleless=100, max_moves=1000)
+    pool = []
+    for ply in range(121):
+        ref.ply(obs=False, mask=False)
+        if ply % 40 == 0:
+            pool.append(ref.export())
+    pool = np.concatenate(pool)
+    rng = np.random.default_rng(seed)
+    return pool[rng.choice(len(pool), size=total, replace=False)]
+
+
+def test_serving_results_same_alone_and_in_the_mix():
+    """Continuous batching over a 4096-slot pool with a small memory budget:
+    every request's final states (and step requests' observations) equal the
+    same request served alone and the oracle's."""
+    rng = np.random.default_rng(5)
+    sizes = [1, 7, 64, 300, 1000, 5, 129, 700, 33, 2, 411, 90]
+    reqs, first, t = [], 0, 0.0
+    for r, b in enumerate(sizes):
+        kind = E.REQ_STEP if r % 2 == 0 else E.REQ_ROLLOUT
+        plies = 1 if kind == E.REQ_STEP else int(rng.integers(1, 41))
+        t += float(rng.exponential(0.002))
+        reqs.append((kind, plies, b, first, t))
+        first += b
+    total = first
+    recs = serving_inputs(total)
+    seed = 2
+    eng = E.Engine(4096, seed, k_battleless=100, max_moves=1000, auto_reset=False)
+    inp = torch.from_numpy(recs).cuda()
+    out_mix = torch.zeros_like(inp)
+    obs_mix = torch.zeros((total, 2, 488, 10, 10), dtype=torch.uint8, device="cuda")
+    budget = 1500 * 1536 + 1000 * 97600          # forces requests to queue
+    res, stats = E.stratego_serve(eng.ctx, reqs, inp, out_mix, obs_mix, mem_budget_bytes=budget,
+                                  realtime=True)
+    assert eng.error() == (0, -1)
+    assert stats["game_steps"] == sum(b * p for _, p, b, _, _ in reqs)
+    assert stats["peak_reserved_bytes"] <= budget
+    for (a, d), q in zip(res, reqs):
+        assert q[4] <= a + 1e-3 and a <= d
+    out_mix_h, obs_mix_h = cpu(out_mix), cpu(obs_mix)
+    for r, q in enumerate(reqs):
+        kind, plies, b, f, _ = q
+        out_one = torch.zeros_like(inp)
+        obs_one = torch.zeros_like(obs_mix)
+        E.stratego_serve(eng.ctx, [(kind, plies, b, f, 0.0)], inp, out_one, obs_one, realtime=False)
+        assert_same(f"request {r} states alone vs mix", cpu(out_one)[f:f + b], out_mix_h[f:f + b])
+        if kind == E.REQ_STEP:
+            assert_same(f"request {r} obs alone vs mix", cpu(obs_one)[f:f + b], obs_mix_h[f:f + b])
+        ref = O.OracleEngine.from_records(recs[f:f + b], seed, k_battleless=100, max_moves=1000)
+        for p in range(plies):
+            rr = ref.ply(obs=(kind == E.REQ_STEP), mask=False)
+        assert_same(f"request {r} vs oracle", out_mix_h[f:f + b], ref.export())
+        if kind == E.REQ_STEP:
+            assert_same(f"request {r} obs vs oracle", obs_mix_h[f:f + b], rr["obs"])
+    eng.close()
