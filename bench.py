@@ -163,7 +163,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--tiling", default=None,
-                    help="G,S: use this games-per-WG / LDS-segment tiling instead of autotuning")
+                    help="G,L: use this games-per-WG / LDS-layout tiling instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the engine shards games across GPUs with no "
@@ -289,7 +289,7 @@ def main():
             "workload": f"{n} games, fused persistent ply kernel (mask, sample, encode both "
                         f"players [2,488,10,10] uint8, step, auto-reset), hipGraph of {P} plies",
             "games": n, "plies_per_graph": P, "k_battleless": K_BATTLELESS,
-            "max_moves": MAX_MOVES, "seed": SEED, "games_per_wg": G, "lds_segments": S,
+            "max_moves": MAX_MOVES, "seed": SEED, "games_per_wg": G, "lds_layout": S,
             "parallelism": "single GPU",
         },
         "p50_ms": percentile(lat, 0.5),
@@ -302,7 +302,7 @@ def main():
         },
         "plain_engine": plain,
         "serving": serving,
-        "autotune": [dict(games_per_wg=g, lds_segments=s, us_per_ply=u) for g, s, u in tune],
+        "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -67,7 +67,8 @@ typedef struct {
   uint64_t seed;          /* Philox4x32-10 key for setups, moves and resampling */
   uint32_t game_id_base;  /* global game id of slot 0; slot i has id base + i */
   int32_t games_per_wg;   /* fused engine tile size G in {1,2,4,8,16}; 0 = default */
-  int32_t lds_segments;   /* obs image staged in S LDS segments, S in {1,2,4,8}; 0 = default */
+  int32_t lds_layout;     /* observation staging in LDS: 1 = bit planes; 2..6 = byte images in
+                             1, 2, 4, 8, 16 channel segments; 0 = default (1) */
   int32_t reserved;
 } stratego_config;
 
@@ -196,22 +197,22 @@ int stratego_serve(stratego_ctx* ctx, const stratego_request* reqs, int32_t nreq
                    int32_t obs_by_slot, int64_t mem_budget_bytes, int32_t realtime,
                    stratego_request_result* results, stratego_serve_stats* stats);
 
-/* Time the fused engine for every (games_per_wg, lds_segments) pair that fits
+/* Time the fused engine for every (games_per_wg, lds_layout) pair that fits
  * the device, plies plies each, restoring the game states afterwards, and
  * adopt the fastest.  report (may be NULL) receives up to max_entries rows of
- * {games_per_wg, lds_segments, microseconds per ply}; returns the number of
+ * {games_per_wg, lds_layout, microseconds per ply}; returns the number of
  * rows through n_entries.  Synchronises the stream. */
 typedef struct {
   int32_t games_per_wg;
-  int32_t lds_segments;
+  int32_t lds_layout;
   double us_per_ply;
 } stratego_tune_entry;
 int stratego_autotune(stratego_ctx* ctx, uint8_t* obs_dev, uint64_t* mask_dev, int32_t plies,
                       stratego_tune_entry* report, int32_t max_entries, int32_t* n_entries);
 
-/* Current fused-engine tiling. */
-int stratego_get_tiling(stratego_ctx* ctx, int32_t* games_per_wg, int32_t* lds_segments);
-int stratego_set_tiling(stratego_ctx* ctx, int32_t games_per_wg, int32_t lds_segments);
+/* Current fused-engine tiling (games per workgroup, LDS layout). */
+int stratego_get_tiling(stratego_ctx* ctx, int32_t* games_per_wg, int32_t* lds_layout);
+int stratego_set_tiling(stratego_ctx* ctx, int32_t games_per_wg, int32_t lds_layout);
 
 /* Synchronise the stream, then report and clear the latched device error:
  * returns STRATEGO_OK, E_ILLEGAL_ACTION or E_BAD_STATE; first_bad_slot (may

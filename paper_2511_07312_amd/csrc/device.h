@@ -49,11 +49,40 @@ constexpr int kSlabCounts = 1600;   // int32 [28]: known[2][12], hidden[2], move
 constexpr int kSlabScratch = 1712;  // uint8 [80]: setup / resample work arrays
 constexpr int kSlabImage = 1792;    // obs image segment (also holds the to-square sets)
 
+// Observation staging layouts in LDS (the autotuner's "LDS layout" knob):
+//   kLayoutBits (1): bit planes, one bit per output byte, both observers
+//     staged at once (6.1 KB each) and expanded to bytes while streaming out;
+//   2..6: byte images of both observers in 1, 2, 4, 8, 16 channel segments.
+constexpr int kLayoutBits = 1;
+__host__ __device__ constexpr bool valid_layout(int L) { return L >= 1 && L <= 6; }
+__host__ __device__ constexpr int segments_of(int L) { return L <= 1 ? 1 : 1 << (L - 2); }
+
+// Channels per image segment (multiples of 4, so segments stay 16-byte aligned).
 __host__ __device__ constexpr int seg_channels_for(int segments) {
-  return segments == 1 ? 488 : segments == 2 ? 244 : segments == 4 ? 124 : 64;
+  return segments == 1 ? 488 : segments == 2 ? 244 : segments == 4 ? 124 : segments == 8 ? 64 : 32;
 }
-__host__ __device__ constexpr int slab_bytes_for(int segments) {
-  return kSlabImage + 100 * seg_channels_for(segments);
+// Bytes of one observer's image segment; both observers' segments are staged.
+__host__ __device__ constexpr int seg_bytes_for(int segments) { return 100 * seg_channels_for(segments); }
+
+// bit-plane layout: plane bit 100*c + f of observer o <=> byte (c, f) is 1 (or
+// 255 / a table value in the special regions); move sources in a side plane
+constexpr int kBitsPlane = 6112;                          // 48800 bits, padded
+constexpr int kBitsMovePlane = 416;                       // 32 x 100 bits, padded
+constexpr int kBitsPlane0 = kSlabImage;
+constexpr int kBitsPlane1 = kBitsPlane0 + kBitsPlane;
+constexpr int kBitsMove0 = kBitsPlane1 + kBitsPlane;
+constexpr int kBitsMove1 = kBitsMove0 + kBitsMovePlane;
+constexpr int kBitsCat0 = kBitsMove1 + kBitsMovePlane;    // uint8 [100] per observer
+constexpr int kBitsCat1 = kBitsCat0 + 112;
+constexpr int kBitsTab = kBitsCat1 + 112;                 // uint64 [2][24]
+constexpr int kBitsSlabBytes = kBitsTab + 2 * 24 * 8;
+
+__host__ __device__ constexpr int slab_bytes_for(int L) {
+  return L == kLayoutBits ? kBitsSlabBytes : kSlabImage + 2 * seg_bytes_for(segments_of(L));
+}
+// LDS bytes that must be zero when a game's encoding starts
+__host__ __device__ constexpr int image_bytes_for(int L) {
+  return L == kLayoutBits ? kBitsCat0 - kSlabImage : 2 * seg_bytes_for(segments_of(L));
 }
 
 enum : int { kReasonNone = 0, kReasonFlag = 1, kReasonForcedWin = 2, kReasonForcedDraw = 3,
@@ -713,20 +742,24 @@ __device__ void compute_probq(const uint8_t* R, uint8_t* slab) {
 }
 
 // ---------------------------------------------------------------- encoding
-// Writes byte v at (channel c, frame square f) of the current image segment
-// when c lies in [c_lo, c_hi).
+// Byte v at (channel c, frame square f) of observer o's image segment, kept
+// only when c lies in [c_lo, c_hi).  Observer 1's segment follows observer 0's.
 struct SegWriter {
   uint8_t* img;
-  int c_lo, c_hi;
-  __device__ __forceinline__ void put(int c, int f, uint8_t v) const {
-    if (c >= c_lo && c < c_hi) img[(c - c_lo) * 100 + f] = v;
+  int c_lo, c_hi, seg_bytes;
+  __device__ __forceinline__ void put(int o, int c, int f, uint8_t v) const {
+    if (c >= c_lo && c < c_hi) img[o * seg_bytes + (c - c_lo) * 100 + f] = v;
   }
   __device__ __forceinline__ bool overlaps(int a, int b) const { return a < c_hi && b > c_lo; }
 };
 
-// Scatter the non-zero bytes of observer o's channels [c_lo, c_hi) into the
-// zeroed image segment (App. C.1 channel table and App. C.2 move planes).
-__device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rules& rules, int o,
+__device__ __forceinline__ int frame_of(int o, int s) { return o == 0 ? s : 99 - s; }
+
+// Scatter the non-zero bytes of both observers' channels [c_lo, c_hi) into the
+// zeroed image segments (App. C.1 channel table, App. C.2 move planes).  Every
+// attribute of a piece appears twice: in its owner's "own" channel and in the
+// opponent's "opponent" channel, each in that observer's frame.
+__device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rules& rules,
                                 const SegWriter& W) {
   const int lane = lane_id();
   const int ply = (int)hdr_u32(R, kOffPly);
@@ -735,82 +768,83 @@ __device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rul
     const uint8_t v41 = (uint8_t)quant255((uint32_t)ply, (uint32_t)rules.max_moves);
     const uint8_t v42 = (uint8_t)quant255(hdr_u32(R, kOffBattleless), (uint32_t)rules.k_battleless);
     for (int f = lane; f < kSquares; f += 64) {
-      W.put(41, f, v41);
-      W.put(42, f, v42);
+      W.put(0, 41, f, v41);
+      W.put(0, 42, f, v42);
+      W.put(1, 41, f, v41);
+      W.put(1, 42, f, v42);
     }
   }
   // squares
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
-    int s = lane + 64 * h;
+    const int s = lane + 64 * h;
     if (s >= kSquares) break;
-    const int f = o == 0 ? s : 99 - s;
     const int id = board_at(R, s);
     if (id == kLake) continue;
     if (id == kEmpty) {
-      W.put(38, f, 1);
+      W.put(0, 38, s, 1);
+      W.put(1, 38, 99 - s, 1);
       continue;
     }
+    const int w = owner(id), e = 1 - w;      // owner and opponent observers
+    const int fw = frame_of(w, s), fe = frame_of(e, s);
     const uint32_t* pw = piece_words(R, id);
     const uint32_t w0 = pw[0];
     const int t = p_type(w0);
-    const bool own = owner(id) == o;
     const bool rev = p_revealed(w0), mv = p_moved(w0);
     if (W.overlaps(0, 41)) {
-      if (own) {
-        W.put(t, f, 1);
-        if (!rev) W.put(36, f, 1);
-        if (mv) W.put(39, f, 1);
-      } else {
-        if (!rev) W.put(37, f, 1);
-        if (mv) W.put(40, f, 1);
-      }
-      const int pbase = own ? 24 : 12;
-      if (rev) {
-        W.put(pbase + t, f, 255);
-      } else {
-        const uint8_t* pq = slab + kSlabProbQ + 24 * owner(id) + 12 * (mv ? 1 : 0);
-        for (int k = 0; k < 12; ++k)
-          if (pq[k]) W.put(pbase + k, f, pq[k]);
+      W.put(w, t, fw, 1);                                  // 0-11 own type
+      if (!rev) { W.put(w, 36, fw, 1); W.put(e, 37, fe, 1); }
+      if (mv) { W.put(w, 39, fw, 1); W.put(e, 40, fe, 1); }
+      if (rev) {                                           // 12-35 known type
+        W.put(w, 24 + t, fw, 255);
+        W.put(e, 12 + t, fe, 255);
+      } else {                                             // 12-35 probabilities
+        const uint8_t* pq = slab + kSlabProbQ + 24 * w + 12 * (mv ? 1 : 0);
+        for (int k = 0; k < 12; ++k) {
+          const uint8_t v = pq[k];
+          if (v) { W.put(w, 24 + k, fw, v); W.put(e, 12 + k, fe, v); }
+        }
       }
     }
-    const int hbase = own ? 43 : 76;
-    if (W.overlaps(hbase, hbase + 33)) {
+    if (W.overlaps(43, 109)) {                             // threat, evade, adjacency
       uint32_t th = pw[1] & 0x7FFu, ev = (pw[1] >> 11) & 0x7FFu, ad = pw[2] & 0x7FFu;
-      while (th) { int j = __ffs(th) - 1; th &= th - 1; W.put(hbase + j, f, 1); }
-      while (ev) { int j = __ffs(ev) - 1; ev &= ev - 1; W.put(hbase + 11 + j, f, 1); }
-      while (ad) { int j = __ffs(ad) - 1; ad &= ad - 1; W.put(hbase + 22 + j, f, 1); }
+      while (th) { int j = __ffs(th) - 1; th &= th - 1; W.put(w, 43 + j, fw, 1); W.put(e, 76 + j, fe, 1); }
+      while (ev) { int j = __ffs(ev) - 1; ev &= ev - 1; W.put(w, 54 + j, fw, 1); W.put(e, 87 + j, fe, 1); }
+      while (ad) { int j = __ffs(ad) - 1; ad &= ad - 1; W.put(w, 65 + j, fw, 1); W.put(e, 98 + j, fe, 1); }
     }
-    const int gbase = own ? 251 : 303;
-    if (W.overlaps(gbase, gbase + 52)) {
+    if (W.overlaps(251, 355)) {                            // protection groups
       uint32_t pr = (pw[2] >> 11) & 0x1FFFu, pa = pw[3] & 0x1FFFu;
       uint32_t bb = (pw[3] >> 13) & 0x1FFFu, ba = (w0 >> 17) & 0x1FFFu;
-      while (pr) { int j = __ffs(pr) - 1; pr &= pr - 1; W.put(gbase + j, f, 1); }
-      while (pa) { int j = __ffs(pa) - 1; pa &= pa - 1; W.put(gbase + 13 + j, f, 1); }
-      while (bb) { int j = __ffs(bb) - 1; bb &= bb - 1; W.put(gbase + 26 + j, f, 1); }
-      while (ba) { int j = __ffs(ba) - 1; ba &= ba - 1; W.put(gbase + 39 + j, f, 1); }
+      while (pr) { int j = __ffs(pr) - 1; pr &= pr - 1; W.put(w, 251 + j, fw, 1); W.put(e, 303 + j, fe, 1); }
+      while (pa) { int j = __ffs(pa) - 1; pa &= pa - 1; W.put(w, 264 + j, fw, 1); W.put(e, 316 + j, fe, 1); }
+      while (bb) { int j = __ffs(bb) - 1; bb &= bb - 1; W.put(w, 277 + j, fw, 1); W.put(e, 329 + j, fe, 1); }
+      while (ba) { int j = __ffs(ba) - 1; ba &= ba - 1; W.put(w, 290 + j, fw, 1); W.put(e, 342 + j, fe, 1); }
     }
-    if (W.overlaps(355, 455)) {
+    if (W.overlaps(355, 455)) {                            // start square of this piece
       const int st = start_sq(id);
-      W.put(355 + (o == 0 ? st : 99 - st), f, 1);
+      W.put(w, 355 + frame_of(w, st), fw, 1);
+      W.put(e, 355 + frame_of(e, st), fe, 1);
     }
   }
   // captured pieces: start squares (109-130) and death square x cause (131-250)
   if (W.overlaps(109, 251)) {
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      int id = lane + 64 * h;
+      const int id = lane + 64 * h;
       if (id >= kPieces) break;
       const uint32_t w0 = piece_words(R, id)[0];
       if (p_alive(w0)) continue;
       const int t = p_type(w0);
       if (t == kFlag) continue;
-      const bool own = owner(id) == o;
-      const int st = start_sq(id);
-      W.put((own ? 109 : 120) + (t == kBomb ? 10 : t), o == 0 ? st : 99 - st, 1);
+      const int w = owner(id), e = 1 - w;
+      const int st = start_sq(id), slot = t == kBomb ? 10 : t;
+      W.put(w, 109 + slot, frame_of(w, st), 1);
+      W.put(e, 120 + slot, frame_of(e, st), 1);
       if (t <= kMarshal) {
         const int cause = (w0 >> 7) & 7, dsq = (w0 >> 10) & 127;
-        W.put((own ? 131 : 191) + 10 * (cause - 1) + t, o == 0 ? dsq : 99 - dsq, 1);
+        W.put(w, 131 + 10 * (cause - 1) + t, frame_of(w, dsq), 1);
+        W.put(e, 191 + 10 * (cause - 1) + t, frame_of(e, dsq), 1);
       }
     }
   }
@@ -819,9 +853,11 @@ __device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rul
     const int rc = R[kOffRingCount];
     if (lane < rc) {
       const int slot = (ply - 1 - lane) & 31;
-      const int fr = R[kOffRing + 2 * slot], tt = R[kOffRing + 2 * slot + 1];
-      W.put(456 + lane, o == 0 ? tt : 99 - tt, 0x01);
-      W.put(456 + lane, o == 0 ? fr : 99 - fr, 0xFF);
+      const int fr = R[kOffRing + 2 * slot], to = R[kOffRing + 2 * slot + 1];
+      W.put(0, 456 + lane, to, 0x01);
+      W.put(0, 456 + lane, fr, 0xFF);
+      W.put(1, 456 + lane, 99 - to, 0x01);
+      W.put(1, 456 + lane, 99 - fr, 0xFF);
     }
   }
 }
@@ -839,47 +875,226 @@ __device__ __forceinline__ void clear_lds(uint8_t* p, int bytes) {
 // Bytes of the 101 destination sets legal_mask_words parks in the image.
 constexpr int kDestSetBytes = 101 * 16;
 
-// Encode both observers of the game staged in R into obs (global, 97600 bytes).
-// Per segment of channels: scatter the non-zero bytes into the (zero) LDS
-// image, then stream it to HBM with non-temporal 16-byte stores, four loads in
-// flight per lane, clearing the image behind the reads.
-__device__ void encode_game(const uint8_t* R, uint8_t* slab, const Rules& rules, int segments,
-                            uint8_t* obs) {
-  const int lane = lane_id();
-  const int segc = seg_channels_for(segments);
-  uint8_t* img = slab + kSlabImage;
-  u32x4* im = reinterpret_cast<u32x4*>(img);
+// Stream `chunks` 16-byte chunks of an LDS image to global memory with
+// non-temporal stores, four loads in flight per lane, clearing behind.
+__device__ __forceinline__ void stream_out(u32x4* im, u32x4* dst, int chunks) {
   const u32x4 z = {0u, 0u, 0u, 0u};
+  int k = lane_id();
+  for (; k + 192 < chunks; k += 256) {
+    u32x4 v0 = im[k], v1 = im[k + 64], v2 = im[k + 128], v3 = im[k + 192];
+    im[k] = z;
+    im[k + 64] = z;
+    im[k + 128] = z;
+    im[k + 192] = z;
+    __builtin_nontemporal_store(v0, dst + k);
+    __builtin_nontemporal_store(v1, dst + k + 64);
+    __builtin_nontemporal_store(v2, dst + k + 128);
+    __builtin_nontemporal_store(v3, dst + k + 192);
+  }
+  for (; k < chunks; k += 64) {
+    u32x4 v = im[k];
+    im[k] = z;
+    __builtin_nontemporal_store(v, dst + k);
+  }
+}
+
+// Encode both observers of the game staged in R into obs (global, 97600
+// bytes) with the byte-image layout: per segment of channels, scatter both
+// observers' non-zero bytes into the zero LDS images, then stream both
+// segments to HBM.
+__device__ void encode_game_bytes(const uint8_t* R, uint8_t* slab, const Rules& rules, int segments,
+                                  uint8_t* obs) {
+  const int segc = seg_channels_for(segments), segb = seg_bytes_for(segments);
+  uint8_t* img = slab + kSlabImage;
 #pragma unroll 1
-  for (int o = 0; o < 2; ++o) {
+  for (int c_lo = 0; c_lo < kChannels; c_lo += segc) {
+    const int c_hi = c_lo + segc < kChannels ? c_lo + segc : kChannels;
+    const int chunks = (c_hi - c_lo) * 100 / 16;
+    SegWriter W{img, c_lo, c_hi, segb};
+    scatter_segment(R, slab, rules, W);
+    wave_sync();
+    stream_out(reinterpret_cast<u32x4*>(img), reinterpret_cast<u32x4*>(obs + c_lo * 100), chunks);
+    stream_out(reinterpret_cast<u32x4*>(img + segb),
+               reinterpret_cast<u32x4*>(obs + kObsPerObserver + c_lo * 100), chunks);
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------- bit planes
+__device__ __forceinline__ void plane_set(uint8_t* slab, int o, int c, int f) {
+  const int bit = 100 * c + f;
+  uint32_t* bm = reinterpret_cast<uint32_t*>(slab + (o ? kBitsPlane1 : kBitsPlane0));
+  atomicOr(&bm[bit >> 5], 1u << (bit & 31));
+}
+
+// 4 bits -> 4 bytes holding 0 or 1
+__device__ __forceinline__ uint32_t expand4(uint32_t n) { return (n * 0x00204081u) & 0x01010101u; }
+
+// Build both observers' bit planes, probability categories and tables in one
+// pass over squares, dead pieces and the move ring (App. C.1, C.2).  Planes
+// must be zero on entry.  Probability channels 12-35 take their hidden-piece
+// values from per-square categories (1/2 opponent hidden moved/unmoved, 3/4
+// own hidden moved/unmoved) and a per-channel table; the planes carry only the
+// 255 of revealed types there.
+__device__ void build_bitplanes(const uint8_t* R, uint8_t* slab) {
+  const int lane = lane_id();
+  const int ply = (int)hdr_u32(R, kOffPly);
 #pragma unroll 1
-    for (int c_lo = 0; c_lo < kChannels; c_lo += segc) {
-      const int c_hi = c_lo + segc < kChannels ? c_lo + segc : kChannels;
-      const int chunks = (c_hi - c_lo) * 100 / 16;
-      SegWriter W{img, c_lo, c_hi};
-      scatter_segment(R, slab, rules, o, W);
-      wave_sync();
-      u32x4* dst = reinterpret_cast<u32x4*>(obs + o * kObsPerObserver + c_lo * 100);
-      int k = lane;
-      for (; k + 192 < chunks; k += 256) {
-        u32x4 v0 = im[k], v1 = im[k + 64], v2 = im[k + 128], v3 = im[k + 192];
-        im[k] = z;
-        im[k + 64] = z;
-        im[k + 128] = z;
-        im[k + 192] = z;
-        __builtin_nontemporal_store(v0, dst + k);
-        __builtin_nontemporal_store(v1, dst + k + 64);
-        __builtin_nontemporal_store(v2, dst + k + 128);
-        __builtin_nontemporal_store(v3, dst + k + 192);
+  for (int h = 0; h < 2; ++h) {
+    const int s = lane + 64 * h;
+    if (s >= kSquares) break;
+    const int id = board_at(R, s);
+    uint8_t cat0 = 0, cat1 = 0;
+    if (id == kEmpty) {
+      plane_set(slab, 0, 38, s);
+      plane_set(slab, 1, 38, 99 - s);
+    } else if (id >= 0) {
+      const int w = owner(id), e = 1 - w;
+      const int fw = frame_of(w, s), fe = frame_of(e, s);
+      const uint32_t* pw = piece_words(R, id);
+      const uint32_t w0 = pw[0];
+      const int t = p_type(w0);
+      const bool rev = p_revealed(w0), mv = p_moved(w0);
+      plane_set(slab, w, t, fw);
+      if (rev) {
+        plane_set(slab, w, 24 + t, fw);
+        plane_set(slab, e, 12 + t, fe);
+      } else {
+        plane_set(slab, w, 36, fw);
+        plane_set(slab, e, 37, fe);
+        const uint8_t own_cat = mv ? 3 : 4, opp_cat = mv ? 1 : 2;
+        if (w == 0) { cat0 = own_cat; cat1 = opp_cat; } else { cat1 = own_cat; cat0 = opp_cat; }
       }
-      for (; k < chunks; k += 64) {
-        u32x4 v = im[k];
-        im[k] = z;
-        __builtin_nontemporal_store(v, dst + k);
+      if (mv) {
+        plane_set(slab, w, 39, fw);
+        plane_set(slab, e, 40, fe);
       }
-      wave_sync();
+      uint32_t th = pw[1] & 0x7FFu, ev = (pw[1] >> 11) & 0x7FFu, ad = pw[2] & 0x7FFu;
+      while (th) { int j = __ffs(th) - 1; th &= th - 1; plane_set(slab, w, 43 + j, fw); plane_set(slab, e, 76 + j, fe); }
+      while (ev) { int j = __ffs(ev) - 1; ev &= ev - 1; plane_set(slab, w, 54 + j, fw); plane_set(slab, e, 87 + j, fe); }
+      while (ad) { int j = __ffs(ad) - 1; ad &= ad - 1; plane_set(slab, w, 65 + j, fw); plane_set(slab, e, 98 + j, fe); }
+      uint32_t pr = (pw[2] >> 11) & 0x1FFFu, pa = pw[3] & 0x1FFFu;
+      uint32_t bb = (pw[3] >> 13) & 0x1FFFu, ba = (w0 >> 17) & 0x1FFFu;
+      while (pr) { int j = __ffs(pr) - 1; pr &= pr - 1; plane_set(slab, w, 251 + j, fw); plane_set(slab, e, 303 + j, fe); }
+      while (pa) { int j = __ffs(pa) - 1; pa &= pa - 1; plane_set(slab, w, 264 + j, fw); plane_set(slab, e, 316 + j, fe); }
+      while (bb) { int j = __ffs(bb) - 1; bb &= bb - 1; plane_set(slab, w, 277 + j, fw); plane_set(slab, e, 329 + j, fe); }
+      while (ba) { int j = __ffs(ba) - 1; ba &= ba - 1; plane_set(slab, w, 290 + j, fw); plane_set(slab, e, 342 + j, fe); }
+      const int st = start_sq(id);
+      plane_set(slab, w, 355 + frame_of(w, st), fw);
+      plane_set(slab, e, 355 + frame_of(e, st), fe);
+    }
+    slab[kBitsCat0 + s] = cat0;
+    slab[kBitsCat1 + 99 - s] = cat1;
+  }
+  // captured pieces: start squares (109-130) and death square x cause (131-250)
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int id = lane + 64 * h;
+    if (id >= kPieces) break;
+    const uint32_t w0 = piece_words(R, id)[0];
+    if (p_alive(w0)) continue;
+    const int t = p_type(w0);
+    if (t == kFlag) continue;
+    const int w = owner(id), e = 1 - w;
+    const int st = start_sq(id), slot = t == kBomb ? 10 : t;
+    plane_set(slab, w, 109 + slot, frame_of(w, st));
+    plane_set(slab, e, 120 + slot, frame_of(e, st));
+    if (t <= kMarshal) {
+      const int cause = (w0 >> 7) & 7, dsq = (w0 >> 10) & 127;
+      plane_set(slab, w, 131 + 10 * (cause - 1) + t, frame_of(w, dsq));
+      plane_set(slab, e, 191 + 10 * (cause - 1) + t, frame_of(e, dsq));
     }
   }
+  // recent moves (456-487): destinations in the planes, sources in the side planes
+  const int rc = R[kOffRingCount];
+  if (lane < rc) {
+    const int slot = (ply - 1 - lane) & 31;
+    const int fr = R[kOffRing + 2 * slot], to = R[kOffRing + 2 * slot + 1];
+    plane_set(slab, 0, 456 + lane, to);
+    plane_set(slab, 1, 456 + lane, 99 - to);
+    uint32_t* m0 = reinterpret_cast<uint32_t*>(slab + kBitsMove0);
+    uint32_t* m1 = reinterpret_cast<uint32_t*>(slab + kBitsMove1);
+    const int b0 = 100 * lane + fr, b1 = 100 * lane + 99 - fr;
+    atomicOr(&m0[b0 >> 5], 1u << (b0 & 31));
+    atomicOr(&m1[b1 >> 5], 1u << (b1 & 31));
+  }
+  // probability tables: entry c-12 of observer o, indexed by category
+  if (lane < 48) {
+    const int o = lane / 24, j = lane % 24;
+    const uint8_t* pq = slab + kSlabProbQ;
+    uint64_t tab;
+    if (j < 12) {   // channel 12 + j: the opponent's pieces, type j
+      const int z = 1 - o;
+      tab = ((uint64_t)pq[24 * z + 12 + j] << 8) | ((uint64_t)pq[24 * z + j] << 16);
+    } else {        // channel 24 + (j - 12): own pieces, type j - 12
+      tab = ((uint64_t)pq[24 * o + 12 + (j - 12)] << 24) | ((uint64_t)pq[24 * o + (j - 12)] << 32);
+    }
+    reinterpret_cast<uint64_t*>(slab + kBitsTab)[lane] = tab;
+  }
+  wave_sync();
+}
+
+// Expand observer o's bit planes to 48800 bytes in global memory: each lane
+// turns 16 plane bits into one 16-byte chunk; consecutive lanes write
+// consecutive chunks (1 KB per wave store).
+__device__ __forceinline__ void stream_bitplanes(const uint8_t* slab, int o, uint32_t c41, uint32_t c42,
+                                                 uint8_t* out) {
+  const uint16_t* bm = reinterpret_cast<const uint16_t*>(slab + (o ? kBitsPlane1 : kBitsPlane0));
+  const uint16_t* mv = reinterpret_cast<const uint16_t*>(slab + (o ? kBitsMove1 : kBitsMove0));
+  const uint8_t* cat = slab + (o ? kBitsCat1 : kBitsCat0);
+  const uint64_t* tab = reinterpret_cast<const uint64_t*>(slab + kBitsTab) + 24 * o;
+  u32x4* dst = reinterpret_cast<u32x4*>(out);
+  constexpr int kChunks = kObsPerObserver / 16;   // 3050
+#pragma unroll 2
+  for (int k = lane_id(); k < kChunks; k += 64) {
+    const uint32_t x = bm[k];
+    uint32_t d[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d[j] = expand4((x >> (4 * j)) & 15u);
+    if (k >= 75 && k < 269) {
+      // channels 12-35 (probabilities, 255 for known types) and 41-42 (fractions)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int b = 16 * k + 4 * j;
+        const int c = b / 100, f0 = b - 100 * c;
+        if (c >= 12 && c < 36) {
+          const uint32_t cats = *reinterpret_cast<const uint32_t*>(cat + f0);
+          const uint64_t tb = tab[c - 12];
+          d[j] = __builtin_amdgcn_perm((uint32_t)(tb >> 32), (uint32_t)tb, cats) | (d[j] * 0xFFu);
+        } else if (c == 41) {
+          d[j] = c41;
+        } else if (c == 42) {
+          d[j] = c42;
+        }
+      }
+    } else if (k >= 2850) {
+      // channels 456-487: +1 destinations from the planes, -1 (0xFF) sources
+      const uint32_t y = mv[k - 2850];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) d[j] |= expand4((y >> (4 * j)) & 15u) * 0xFFu;
+    }
+    const u32x4 v = {d[0], d[1], d[2], d[3]};
+    __builtin_nontemporal_store(v, dst + k);
+  }
+}
+
+__device__ void encode_game_bits(const uint8_t* R, uint8_t* slab, const Rules& rules, uint8_t* obs) {
+  clear_lds(slab + kSlabImage, image_bytes_for(kLayoutBits));
+  build_bitplanes(R, slab);
+  const uint32_t c41 = 0x01010101u * quant255(hdr_u32(R, kOffPly), (uint32_t)rules.max_moves);
+  const uint32_t c42 = 0x01010101u * quant255(hdr_u32(R, kOffBattleless), (uint32_t)rules.k_battleless);
+  stream_bitplanes(slab, 0, c41, c42, obs);
+  stream_bitplanes(slab, 1, c41, c42, obs + kObsPerObserver);
+  wave_sync();
+}
+
+// Encode both observers with the given LDS layout.  The byte-image layouts
+// expect a zero image on entry and leave it zero; the bit-plane layout clears
+// its planes itself.
+__device__ void encode_game(const uint8_t* R, uint8_t* slab, const Rules& rules, int layout,
+                            uint8_t* obs) {
+  if (layout == kLayoutBits) encode_game_bits(R, slab, rules, obs);
+  else encode_game_bytes(R, slab, rules, segments_of(layout), obs);
 }
 
 // ---------------------------------------------------------------- resampling

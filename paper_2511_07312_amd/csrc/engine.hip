@@ -47,18 +47,19 @@ struct PlyArgs {
   unsigned long long* ts;
   Rules rules;
   int32_t games_per_tile;
-  int32_t segments;
+  int32_t layout;     // observation staging layout in LDS
 };
 
-template <int MODE>
-__global__ void __launch_bounds__(256) k_ply(PlyArgs a) {
+template <int MODE, bool BITS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ply(PlyArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
-  uint8_t* slab = smem + wave * slab_bytes_for(a.segments);
+  uint8_t* slab = smem + wave * slab_bytes_for(a.layout);
   uint8_t* R = slab;
   if (a.ts && threadIdx.x == 0) atomicMin(&a.ts[0], (unsigned long long)wall_clock64());
   const bool encode = (MODE & kDoEncode) && a.obs;
-  if (encode) clear_lds(slab + kSlabImage, 100 * seg_channels_for(a.segments));
+  const bool byte_image = encode && a.layout != kLayoutBits;
+  if (byte_image) clear_lds(slab + kSlabImage, image_bytes_for(a.layout));
   const int G = a.games_per_tile;
   const int ntiles = (a.n + G - 1) / G;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -90,12 +91,13 @@ __global__ void __launch_bounds__(256) k_ply(PlyArgs a) {
           if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
         }
         wave_sync();
-        if (encode) clear_lds(slab + kSlabImage, kDestSetBytes);
+        if (byte_image) clear_lds(slab + kSlabImage, kDestSetBytes);
       }
       if (MODE & kStepFromInput) action = a.actions_in[i];
       if (encode) {
         compute_probq(R, slab);
-        encode_game(R, slab, a.rules, a.segments, a.obs + (size_t)oi * kObsPerGame);
+        if (BITS) encode_game_bits(R, slab, a.rules, a.obs + (size_t)oi * kObsPerGame);
+        else encode_game_bytes(R, slab, a.rules, segments_of(a.layout), a.obs + (size_t)oi * kObsPerGame);
       }
       if (MODE & kDoStep) {
         StepOut o = step_game(R, slab + kSlabScratch, a.rules, action);
@@ -266,9 +268,8 @@ inline Rules rules_of(const stratego_ctx* c) {
 
 inline int grid_for(int n, int per_block) { return (n + per_block - 1) / per_block; }
 
-bool valid_tiling(int G, int S) {
-  return (G == 1 || G == 2 || G == 4 || G == 8 || G == 16) &&
-         (S == 1 || S == 2 || S == 4 || S == 8);
+bool valid_tiling(int G, int L) {
+  return (G == 1 || G == 2 || G == 4 || G == 8 || G == 16) && valid_layout(L);
 }
 
 inline int waves_for(int G) { return G < 4 ? G : 4; }
@@ -280,17 +281,26 @@ int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S
   const int W = (mode == kFused) ? waves_for(G) : 4;
   const int tile = (mode == kFused) ? G : 4;
   a.games_per_tile = tile;
-  a.segments = S;
+  a.layout = S;
   const size_t lds = (size_t)W * slab_bytes_for(S);
   if (lds > c->max_lds) return STRATEGO_E_INVAL;
   int ntiles = grid_for(a.n, tile);
   int grid = ntiles;
+  const bool bits = S == kLayoutBits;
   const void* fn = nullptr;
   switch (mode) {
-    case kFused: fn = reinterpret_cast<const void*>(&k_ply<kFused>); break;
-    case kDoMask: fn = reinterpret_cast<const void*>(&k_ply<kDoMask>); break;
-    case kDoEncode: fn = reinterpret_cast<const void*>(&k_ply<kDoEncode>); break;
-    case kDoStep | kStepFromInput: fn = reinterpret_cast<const void*>(&k_ply<kDoStep | kStepFromInput>); break;
+    case kFused:
+      fn = bits ? reinterpret_cast<const void*>(&k_ply<kFused, true>)
+                : reinterpret_cast<const void*>(&k_ply<kFused, false>);
+      break;
+    case kDoMask: fn = reinterpret_cast<const void*>(&k_ply<kDoMask, false>); break;
+    case kDoEncode:
+      fn = bits ? reinterpret_cast<const void*>(&k_ply<kDoEncode, true>)
+                : reinterpret_cast<const void*>(&k_ply<kDoEncode, false>);
+      break;
+    case kDoStep | kStepFromInput:
+      fn = reinterpret_cast<const void*>(&k_ply<kDoStep | kStepFromInput, false>);
+      break;
     default: return STRATEGO_E_INVAL;
   }
   if (persistent) {
@@ -301,14 +311,8 @@ int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S
     if (grid > cap) grid = cap;
   }
   if (grid <= 0) return STRATEGO_OK;
-  switch (mode) {
-    case kFused: hipLaunchKernelGGL(k_ply<kFused>, dim3(grid), dim3(64 * W), lds, s, a); break;
-    case kDoMask: hipLaunchKernelGGL(k_ply<kDoMask>, dim3(grid), dim3(64 * W), lds, s, a); break;
-    case kDoEncode: hipLaunchKernelGGL(k_ply<kDoEncode>, dim3(grid), dim3(64 * W), lds, s, a); break;
-    default:
-      hipLaunchKernelGGL((k_ply<kDoStep | kStepFromInput>), dim3(grid), dim3(64 * W), lds, s, a);
-      break;
-  }
+  void* args[] = {&a};
+  if (hipLaunchKernel(fn, dim3(grid), dim3(64 * W), args, lds, s) != hipSuccess) return STRATEGO_E_HIP;
   return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
 }
 
@@ -372,8 +376,8 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
   if (cfg->num_games <= 0 || cfg->k_battleless <= 0 || cfg->max_moves <= 0 ||
       cfg->max_moves > 32767 || (cfg->auto_reset != 0 && cfg->auto_reset != 1))
     return STRATEGO_E_INVAL;
-  int G = cfg->games_per_wg ? cfg->games_per_wg : 4;
-  int S = cfg->lds_segments ? cfg->lds_segments : 4;
+  int G = cfg->games_per_wg ? cfg->games_per_wg : 1;
+  int S = cfg->lds_layout ? cfg->lds_layout : kLayoutBits;
   if (!valid_tiling(G, S)) return STRATEGO_E_INVAL;
   stratego_ctx* c = new (std::nothrow) stratego_ctx();
   if (!c) return STRATEGO_E_NOMEM;
@@ -421,10 +425,12 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
     return STRATEGO_E_NOMEM;
   }
   // kernels whose dynamic LDS may exceed the default limit
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ply<kFused>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->max_lds);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ply<kDoEncode>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->max_lds);
+  const void* big_lds[] = {reinterpret_cast<const void*>(&k_ply<kFused, true>),
+                           reinterpret_cast<const void*>(&k_ply<kFused, false>),
+                           reinterpret_cast<const void*>(&k_ply<kDoEncode, true>),
+                           reinterpret_cast<const void*>(&k_ply<kDoEncode, false>)};
+  for (const void* f : big_lds)
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->max_lds);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->err, 2, INT_MAX);
   int rc = stratego_reset(c, nullptr, cfg->num_games, nullptr);
   if (rc != STRATEGO_OK) { stratego_destroy(c); return rc; }
@@ -451,7 +457,7 @@ int stratego_legal_mask(stratego_ctx* c, uint64_t* mask, int16_t* num_legal) {
   PlyArgs a = base_args(c);
   a.mask = mask;
   a.num_legal = num_legal;
-  return launch_ply(c, c->stream, kDoMask, a, 4, 8, false);
+  return launch_ply(c, c->stream, kDoMask, a, 4, 6, false);
 }
 
 int stratego_sample_actions(stratego_ctx* c, const uint64_t* mask, const int16_t* num_legal,
@@ -471,7 +477,7 @@ int stratego_step(stratego_ctx* c, const int16_t* actions, int8_t* done, int8_t*
   a.outcome = outcome;
   a.reason = reason;
   a.ep_len = ep_len;
-  int rc = launch_ply(c, c->stream, kDoStep | kStepFromInput, a, 4, 8, false);
+  int rc = launch_ply(c, c->stream, kDoStep | kStepFromInput, a, 4, 6, false);
   if (rc == STRATEGO_OK) c->steps += c->cfg.num_games;
   return rc;
 }
@@ -480,7 +486,7 @@ int stratego_encode_obs(stratego_ctx* c, uint8_t* obs) {
   if (!c || !obs) return STRATEGO_E_INVAL;
   PlyArgs a = base_args(c);
   a.obs = obs;
-  return launch_ply(c, c->stream, kDoEncode, a, 4, 4, false);
+  return launch_ply(c, c->stream, kDoEncode, a, 4, kLayoutBits, false);
 }
 
 int stratego_export_states(stratego_ctx* c, void* states) {
@@ -781,17 +787,19 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   const int Gs[5] = {1, 2, 4, 8, 16};
-  const int Ss[4] = {1, 2, 4, 8};
+  const int Ss[6] = {1, 2, 3, 4, 5, 6};
   int best_G = c->G, best_S = c->S, count = 0;
   float best = 1e30f;
   int rc = STRATEGO_OK;
   for (int gi = 0; gi < 5 && rc == STRATEGO_OK; ++gi) {
-    for (int si = 0; si < 4 && rc == STRATEGO_OK; ++si) {
+    for (int si = 0; si < 6 && rc == STRATEGO_OK; ++si) {
       const int G = Gs[gi], S = Ss[si];
       if (lds_for(G, S) > c->max_lds) continue;
       int per_cu = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_ply<kFused>),
-                                                       64 * waves_for(G), lds_for(G, S)) != hipSuccess ||
+      const void* fused = S == kLayoutBits ? reinterpret_cast<const void*>(&k_ply<kFused, true>)
+                                           : reinterpret_cast<const void*>(&k_ply<kFused, false>);
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64 * waves_for(G), lds_for(G, S)) !=
+              hipSuccess ||
           per_cu <= 0)
         continue;
       // warm-up ply, then the timed plies
@@ -808,7 +816,7 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
       const float us = 1000.f * ms / (float)plies;
       if (report && count < max_entries) {
         report[count].games_per_wg = G;
-        report[count].lds_segments = S;
+        report[count].lds_layout = S;
         report[count].us_per_ply = us;
       }
       ++count;

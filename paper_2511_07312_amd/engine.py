@@ -39,12 +39,12 @@ class StrategoConfig(ctypes.Structure):
     _fields_ = [("num_games", ctypes.c_int32), ("k_battleless", ctypes.c_int32),
                 ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("game_id_base", ctypes.c_uint32),
-                ("games_per_wg", ctypes.c_int32), ("lds_segments", ctypes.c_int32),
+                ("games_per_wg", ctypes.c_int32), ("lds_layout", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
-    _fields_ = [("games_per_wg", ctypes.c_int32), ("lds_segments", ctypes.c_int32),
+    _fields_ = [("games_per_wg", ctypes.c_int32), ("lds_layout", ctypes.c_int32),
                 ("us_per_ply", ctypes.c_double)]
 
 
@@ -138,9 +138,9 @@ def _stream():
 
 # ------------------------------------------------------------------ C-ABI mirrors
 def stratego_init(num_games, seed, k_battleless=100, max_moves=4000, auto_reset=False,
-                  game_id_base=0, games_per_wg=0, lds_segments=0):
+                  game_id_base=0, games_per_wg=0, lds_layout=0):
     cfg = StrategoConfig(int(num_games), int(k_battleless), int(max_moves), int(bool(auto_reset)),
-                         int(seed), int(game_id_base), int(games_per_wg), int(lds_segments), 0)
+                         int(seed), int(game_id_base), int(games_per_wg), int(lds_layout), 0)
     ctx = ctypes.c_void_p()
     _check(load_library().stratego_init(ctypes.byref(cfg), _stream(), ctypes.byref(ctx)),
            "stratego_init")
@@ -237,7 +237,7 @@ def stratego_autotune(ctx, obs, mask, plies=3, max_entries=32):
     _check(load_library().stratego_autotune(ctx, _ptr(obs, torch.uint8, None, "obs"),
                                             _ptr(mask, torch.int64, None, "mask"), int(plies), rep,
                                             max_entries, ctypes.byref(n)), "stratego_autotune")
-    return [(rep[i].games_per_wg, rep[i].lds_segments, rep[i].us_per_ply) for i in range(n.value)]
+    return [(rep[i].games_per_wg, rep[i].lds_layout, rep[i].us_per_ply) for i in range(n.value)]
 
 
 def stratego_serve(ctx, requests, in_states, out_states, obs_out=None, obs_by_slot=False,
@@ -269,8 +269,8 @@ def stratego_get_tiling(ctx):
     return g.value, s.value
 
 
-def stratego_set_tiling(ctx, games_per_wg, lds_segments):
-    _check(load_library().stratego_set_tiling(ctx, int(games_per_wg), int(lds_segments)),
+def stratego_set_tiling(ctx, games_per_wg, lds_layout):
+    _check(load_library().stratego_set_tiling(ctx, int(games_per_wg), int(lds_layout)),
            "stratego_set_tiling")
 
 
@@ -296,11 +296,11 @@ class Engine:
     """N games on the current GPU with preallocated output tensors."""
 
     def __init__(self, num_games, seed, k_battleless=100, max_moves=1000, auto_reset=False,
-                 game_id_base=0, games_per_wg=0, lds_segments=0, device="cuda"):
+                 game_id_base=0, games_per_wg=0, lds_layout=0, device="cuda"):
         self.n = int(num_games)
         self.device = torch.device(device)
         self.ctx = stratego_init(num_games, seed, k_battleless, max_moves, auto_reset,
-                                 game_id_base, games_per_wg, lds_segments)
+                                 game_id_base, games_per_wg, lds_layout)
         n, d = self.n, self.device
         self.mask = torch.empty((n, MASK_WORDS), dtype=torch.int64, device=d)
         self.num_legal = torch.empty(n, dtype=torch.int16, device=d)

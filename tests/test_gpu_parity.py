@@ -55,13 +55,18 @@ def test_plain_engine_256_games_200_plies():
 
 
 # ---------------------------------------------------------------- fused engine
-@pytest.mark.parametrize("G,S", [(1, 1), (2, 2), (4, 4), (8, 8), (16, 8), (4, 8)])
-def test_fused_engine_every_tiling(G, S):
+# (games per workgroup, LDS layout): layout 1 = bit planes, 2..6 = byte images
+# in 1, 2, 4, 8, 16 channel segments
+TILINGS = [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (1, 2), (2, 3), (4, 4), (8, 5), (16, 6)]
+
+
+@pytest.mark.parametrize("G,L", TILINGS)
+def test_fused_engine_every_tiling(G, L):
     """Fused persistent kernel, auto-reset on: per ply mask, actions, obs, step
-    outputs and states equal the oracle for every (games per WG, LDS segments)."""
-    n, seed, plies = 1000, 3, 40 if (G, S) != (4, 4) else 160
+    outputs and states equal the oracle for every (games per WG, LDS layout)."""
+    n, seed, plies = 1000, 3, 40 if (G, L) != (1, 1) else 160
     eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True,
-                   games_per_wg=G, lds_segments=S)
+                   games_per_wg=G, lds_layout=L)
     ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
     for ply in range(plies):
         E.stratego_run_plies(eng.ctx, 1, mask=eng.mask, num_legal=eng.num_legal,
