@@ -399,6 +399,19 @@ def test_evasion_adjacency_and_empty_square_protection():
     assert nonzero_history(pcs[maj]) == {}
 
 
+def test_attacking_the_threatener_is_not_an_evasion():
+    # blue's hidden Major moved next to red's Captain; the Captain attacks it
+    rec = make_record([dict(sq=sq(3, 1), owner=0, type="Captain"),
+                       dict(sq=sq(4, 1), owner=1, type="Major", moved=1),
+                       dict(sq=sq(0, 9), owner=0, type="Flag"),
+                       dict(sq=sq(9, 9), owner=1, type="Flag")],
+                      ply=2, moves=[(5, 15), (51, 41)])
+    cap = board(rec)[31]
+    pcs, _, _ = run_and_pieces(rec, 100 * 31 + 41)
+    assert pcs[cap]["alive"] == 0 and pcs[cap]["death_cause"] == 3
+    assert pcs[cap]["evade"] == 0 and pcs[cap]["adj"] == 0
+
+
 def test_protection_of_a_piece_against_revealed_general():
     rec = make_record([dict(sq=sq(3, 4), owner=0, type="Sergeant"),
                        dict(sq=sq(2, 5), owner=0, type="Captain"),
