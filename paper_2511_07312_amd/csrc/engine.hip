@@ -50,34 +50,78 @@ struct PlyArgs {
   int32_t layout;     // observation staging layout in LDS
 };
 
+// Per-wave LDS: the slab of the layout plus a spare record buffer.  While a
+// game is processed, the next game's record is fetched into registers early
+// and parked in the spare buffer before the observation stream starts, so no
+// global load is waited on right after a burst of stores (on gfx950 one
+// counter tracks both, and waiting for a load would also drain the stores).
+__host__ __device__ constexpr int wave_lds_bytes(int layout) { return slab_bytes_for(layout) + kRecordBytes; }
+
 template <int MODE, bool BITS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ply(PlyArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
-  uint8_t* slab = smem + wave * slab_bytes_for(a.layout);
-  uint8_t* R = slab;
+  uint8_t* slab = smem + wave * wave_lds_bytes(a.layout);
+  // the two record buffers are slab + 0 and slab + spare; offsets (not a
+  // pointer array) keep every access an LDS instruction
+  const int spare = slab_bytes_for(a.layout);
   if (a.ts && threadIdx.x == 0) atomicMin(&a.ts[0], (unsigned long long)wall_clock64());
   const bool encode = (MODE & kDoEncode) && a.obs;
   const bool byte_image = encode && a.layout != kLayoutBits;
   if (byte_image) clear_lds(slab + kSlabImage, image_bytes_for(a.layout));
   const int G = a.games_per_tile;
   const int ntiles = (a.n + G - 1) / G;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    for (int gi = wave; gi < G; gi += W) {
-      const int i = tile * G + gi;
-      if (i >= a.n) break;
-      const int slot = a.slots ? a.slots[i] : i;
-      if (slot < 0 || slot >= a.total) {
-        if (lane == 0) atomicMin(&a.err[1], i);
-        continue;
+  // this wave's games: tiles blockIdx.x, +gridDim.x, ...; in a tile, every W-th game
+  int tile = blockIdx.x, gi = wave;
+  int i = tile < ntiles ? tile * G + gi : a.n;
+  bool have = i < a.n;
+  int slot = have ? (a.slots ? a.slots[i] : i) : 0;
+  bool slot_ok = have && slot >= 0 && slot < a.total;
+  if (slot_ok) load_record(slab, a.states + (size_t)slot * kRecordBytes);
+  int cur = 0;   // offset of the current record buffer: 0 or spare
+  while (have) {
+    int ngi = gi + W, ntile = tile;
+    if (ngi >= G) { ngi = wave; ntile += gridDim.x; }
+    const int inext = ntile < ntiles ? ntile * G + ngi : a.n;
+    const bool next_have = inext < a.n;
+    int next_slot = 0;
+    bool next_ok = false;
+    if (next_have) {
+      next_slot = a.slots ? a.slots[inext] : inext;
+      next_ok = next_slot >= 0 && next_slot < a.total;
+    }
+    uint4 p0 = make_uint4(0, 0, 0, 0), p1 = make_uint4(0, 0, 0, 0);
+    bool fetched = false;
+    auto fetch_next = [&]() {
+      if (next_ok && !fetched) {
+        const uint4* src = reinterpret_cast<const uint4*>(a.states + (size_t)next_slot * kRecordBytes);
+        p0 = src[lane];
+        if (lane < 32) p1 = src[64 + lane];
       }
+      fetched = true;
+    };
+    bool parked = false;
+    auto park_next = [&]() {
+      fetch_next();
+      if (next_ok && !parked) {
+        uint4* dst = reinterpret_cast<uint4*>(slab + (spare - cur));
+        dst[lane] = p0;
+        if (lane < 32) dst[64 + lane] = p1;
+      }
+      parked = true;
+    };
+    if (!slot_ok) {
+      if (lane == 0) atomicMin(&a.err[1], i);
+      park_next();
+    } else {
+      uint8_t* R = slab + cur;
       uint8_t* gstate = a.states + (size_t)slot * kRecordBytes;
       const int oi = a.out_index ? a.out_index[i] : i;
-      load_record(R, gstate);
       int action = -1;
       if (MODE & kDoMask) {
         uint64_t w[3];
         const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
+        fetch_next();
         if (a.mask) {
           uint64_t* m = a.mask + (size_t)oi * kMaskWords;
 #pragma unroll
@@ -93,6 +137,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         wave_sync();
         if (byte_image) clear_lds(slab + kSlabImage, kDestSetBytes);
       }
+      park_next();
       if (MODE & kStepFromInput) action = a.actions_in[i];
       if (encode) {
         compute_probq(R, slab);
@@ -112,8 +157,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         wave_sync();
         store_record(gstate, R);
       }
-      wave_sync();
     }
+    wave_sync();
+    i = inext;
+    tile = ntile;
+    gi = ngi;
+    slot = next_slot;
+    slot_ok = next_ok;
+    have = next_have;
+    cur = spare - cur;
   }
   if (a.ts) {
     __syncthreads();
@@ -275,14 +327,14 @@ bool valid_tiling(int G, int L) {
 inline int waves_for(int G) { return G < 4 ? G : 4; }
 
 // Dynamic LDS of one fused-engine workgroup.
-inline size_t lds_for(int G, int S) { return (size_t)waves_for(G) * slab_bytes_for(S); }
+inline size_t lds_for(int G, int S) { return (size_t)waves_for(G) * wave_lds_bytes(S); }
 
 int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent) {
   const int W = (mode == kFused) ? waves_for(G) : 4;
   const int tile = (mode == kFused) ? G : 4;
   a.games_per_tile = tile;
   a.layout = S;
-  const size_t lds = (size_t)W * slab_bytes_for(S);
+  const size_t lds = (size_t)W * wave_lds_bytes(S);
   if (lds > c->max_lds) return STRATEGO_E_INVAL;
   int ntiles = grid_for(a.n, tile);
   int grid = ntiles;
