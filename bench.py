@@ -297,6 +297,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per ply launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+            "algorithmic_bytes_per_launch": BYTES_PER_GAME_STEP * n,
             "kernel": "k_ply<15> (fused ply)", "bytes_per_game_step": BYTES_PER_GAME_STEP,
             "kernel_ms_device_timestamps": kernel_ms,
         },
