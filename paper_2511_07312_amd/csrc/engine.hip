@@ -45,6 +45,7 @@ struct PlyArgs {
   int16_t* ep_len;
   int32_t* err;
   unsigned long long* ts;
+  unsigned int* tickets;   // this ply's work counter (persistent launches), else NULL
   Rules rules;
   int32_t games_per_tile;
   int32_t layout;     // observation staging layout in LDS
@@ -71,8 +72,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   if (byte_image) clear_lds(slab + kSlabImage, image_bytes_for(a.layout));
   const int G = a.games_per_tile;
   const int ntiles = (a.n + G - 1) / G;
-  // this wave's games: tiles blockIdx.x, +gridDim.x, ...; in a tile, every W-th game
-  int tile = blockIdx.x, gi = wave;
+  // Work distribution.  Persistent launches: each wave takes chunks of G
+  // consecutive games from the ply's ticket counter, in address order, as it
+  // becomes free.  Otherwise: tiles blockIdx.x, +gridDim.x, ...; in a tile,
+  // every W-th game.
+  const bool dynamic = a.tickets != nullptr;
+  auto grab = [&]() -> int {
+    int t = 0;
+    if (lane == 0) t = (int)atomicAdd(a.tickets, 1u);
+    return __shfl(t, 0, 64);
+  };
+  int tile, gi;
+  if (dynamic) { tile = grab(); gi = 0; }
+  else { tile = blockIdx.x; gi = wave; }
+  const int step_gi = dynamic ? 1 : W;
   int i = tile < ntiles ? tile * G + gi : a.n;
   bool have = i < a.n;
   int slot = have ? (a.slots ? a.slots[i] : i) : 0;
@@ -80,19 +93,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   if (slot_ok) load_record(slab, a.states + (size_t)slot * kRecordBytes);
   int cur = 0;   // offset of the current record buffer: 0 or spare
   while (have) {
-    int ngi = gi + W, ntile = tile;
-    if (ngi >= G) { ngi = wave; ntile += gridDim.x; }
-    const int inext = ntile < ntiles ? ntile * G + ngi : a.n;
-    const bool next_have = inext < a.n;
+    // the next game of this wave (its chunk is grabbed only when needed)
+    int ngi = gi + step_gi, ntile = tile;
+    bool need_grab = false;
+    if (ngi >= G || tile * G + ngi >= a.n) {
+      ngi = dynamic ? 0 : wave;
+      if (dynamic) need_grab = true;
+      else ntile += gridDim.x;
+    }
+    int inext = a.n;
+    bool next_have = false, resolved = false;
     int next_slot = 0;
     bool next_ok = false;
-    if (next_have) {
-      next_slot = a.slots ? a.slots[inext] : inext;
-      next_ok = next_slot >= 0 && next_slot < a.total;
-    }
+    auto resolve_next = [&]() {
+      if (resolved) return;
+      resolved = true;
+      if (need_grab) ntile = grab();
+      inext = ntile < ntiles ? ntile * G + ngi : a.n;
+      next_have = inext < a.n;
+      if (next_have) {
+        next_slot = a.slots ? a.slots[inext] : inext;
+        next_ok = next_slot >= 0 && next_slot < a.total;
+      }
+    };
+    if (!need_grab) resolve_next();
     uint4 p0 = make_uint4(0, 0, 0, 0), p1 = make_uint4(0, 0, 0, 0);
     bool fetched = false;
     auto fetch_next = [&]() {
+      resolve_next();
       if (next_ok && !fetched) {
         const uint4* src = reinterpret_cast<const uint4*>(a.states + (size_t)next_slot * kRecordBytes);
         p0 = src[lane];
@@ -158,6 +186,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         store_record(gstate, R);
       }
     }
+    resolve_next();
     wave_sync();
     i = inext;
     tile = ntile;
@@ -300,6 +329,7 @@ struct stratego_ctx {
   uint8_t* backup;   // copy of the states while the autotuner runs
   int32_t* err;
   unsigned long long* ts;
+  unsigned int* tickets;   // per-ply work counters of the persistent fused kernel
   int32_t* srv_dev;    // serving slot lists, 4 x N
   int32_t* srv_host;   // pinned host staging of the same lists
   int64_t steps;
@@ -382,6 +412,11 @@ PlyArgs base_args(stratego_ctx* c) {
 int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t* slots, int32_t n,
                   uint64_t* mask, int16_t* num_legal, int16_t* actions, uint8_t* obs, int8_t* done,
                   int8_t* outcome, uint8_t* reason, int16_t* ep_len, bool timed, int G, int S) {
+  if (nplies > kMaxTimedPlies) return STRATEGO_E_INVAL;
+  // zero the per-ply work counters (a kernel, so the step can sit in a graph)
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nplies, 256)), dim3(256), 0, s,
+                     reinterpret_cast<int32_t*>(c->tickets), nplies, 0);
+  if (hipGetLastError() != hipSuccess) return STRATEGO_E_HIP;
   if (timed) {
     hipLaunchKernelGGL(k_ts_init, dim3(grid_for(nplies, 256)), dim3(256), 0, s, c->ts, nplies);
     if (hipGetLastError() != hipSuccess) return STRATEGO_E_HIP;
@@ -400,6 +435,7 @@ int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t*
     a.reason = reason;
     a.ep_len = ep_len;
     a.ts = timed ? c->ts + 2 * p : nullptr;
+    a.tickets = c->tickets + p;
     int rc = launch_ply(c, s, kFused, a, G, S, true);
     if (rc != STRATEGO_OK) return rc;
   }
@@ -463,6 +499,13 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
     (void)hipFree(c->states); (void)hipFree(c->backup); (void)hipFree(c->err); (void)hipFree(c->ts);
     delete c;
     return STRATEGO_E_HIP;
+  }
+  if (hipMalloc(&c->tickets, sizeof(unsigned int) * kMaxTimedPlies) != hipSuccess) {
+    c->tickets = nullptr;
+    c->srv_dev = nullptr;
+    c->srv_host = nullptr;
+    stratego_destroy(c);
+    return STRATEGO_E_NOMEM;
   }
   const size_t lists = 4 * (size_t)cfg->num_games * sizeof(int32_t);
   if (hipMalloc(&c->srv_dev, lists) != hipSuccess) {
@@ -558,10 +601,17 @@ int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t*
   const bool timed = ply_ns != nullptr;
   const int n = c->cfg.num_games;
   if (!use_graph) {
-    int rc = enqueue_plies(c, c->stream, nplies, nullptr, n, mask, num_legal, actions, obs, done,
-                           outcome, reason, ep_len, timed, c->G, c->S);
-    if (rc != STRATEGO_OK) return rc;
+    for (int32_t p0 = 0; p0 < nplies; p0 += kMaxTimedPlies) {
+      const int32_t np = nplies - p0 < kMaxTimedPlies ? nplies - p0 : kMaxTimedPlies;
+      const size_t off = (size_t)p0 * n;
+      int rc = enqueue_plies(c, c->stream, np, nullptr, n, mask, num_legal, actions ? actions + off : nullptr,
+                             obs, done ? done + off : nullptr, outcome ? outcome + off : nullptr,
+                             reason ? reason + off : nullptr, ep_len ? ep_len + off : nullptr, timed, c->G,
+                             c->S);
+      if (rc != STRATEGO_OK) return rc;
+    }
   } else {
+    if (nplies > kMaxTimedPlies) return STRATEGO_E_INVAL;
     const void* key[9] = {mask, num_legal, actions, obs, done, outcome, reason, ep_len,
                           timed ? (const void*)c->ts : nullptr};
     hipGraphExec_t exec = nullptr;
@@ -613,10 +663,16 @@ int stratego_run_plies_slots(stratego_ctx* c, const int32_t* slots, int32_t nslo
                              int8_t* outcome, uint8_t* reason, int16_t* ep_len) {
   if (!c || !slots || nslots < 0 || nslots > c->cfg.num_games || nplies < 0) return STRATEGO_E_INVAL;
   if (nslots == 0 || nplies == 0) return STRATEGO_OK;
-  int rc = enqueue_plies(c, c->stream, nplies, slots, nslots, mask, nullptr, actions, obs, done, outcome,
-                         reason, ep_len, false, c->G, c->S);
-  if (rc == STRATEGO_OK) c->steps += (int64_t)nplies * nslots;
-  return rc;
+  for (int32_t p0 = 0; p0 < nplies; p0 += kMaxTimedPlies) {
+    const int32_t np = nplies - p0 < kMaxTimedPlies ? nplies - p0 : kMaxTimedPlies;
+    const size_t off = (size_t)p0 * nslots;
+    int rc = enqueue_plies(c, c->stream, np, slots, nslots, mask, nullptr, actions ? actions + off : nullptr,
+                           obs, done ? done + off : nullptr, outcome ? outcome + off : nullptr,
+                           reason ? reason + off : nullptr, ep_len ? ep_len + off : nullptr, false, c->G, c->S);
+    if (rc != STRATEGO_OK) return rc;
+  }
+  c->steps += (int64_t)nplies * nslots;
+  return STRATEGO_OK;
 }
 
 int stratego_reset_resampled(stratego_ctx* c, const void* src, int32_t nsrc, int32_t per,
@@ -913,6 +969,7 @@ int stratego_destroy(stratego_ctx* c) {
   for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
   c->graphs.clear();
   (void)hipStreamDestroy(c->capture_stream);
+  if (c->tickets) (void)hipFree(c->tickets);
   if (c->srv_dev) (void)hipFree(c->srv_dev);
   if (c->srv_host) (void)hipHostFree(c->srv_host);
   (void)hipFree(c->states);
