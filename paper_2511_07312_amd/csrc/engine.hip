@@ -354,13 +354,21 @@ bool valid_tiling(int G, int L) {
   return (G == 1 || G == 2 || G == 4 || G == 8 || G == 16) && valid_layout(L);
 }
 
-inline int waves_for(int G) { return G < 4 ? G : 4; }
+// Waves per workgroup: four when their LDS fits, else two, else one; each wave
+// takes its own chunks of G games.
+size_t g_max_lds = 65536;
+inline int waves_for(int G, int S) {
+  (void)G;
+  for (int w = 4; w > 1; w >>= 1)
+    if ((size_t)w * wave_lds_bytes(S) <= g_max_lds) return w;
+  return 1;
+}
 
 // Dynamic LDS of one fused-engine workgroup.
-inline size_t lds_for(int G, int S) { return (size_t)waves_for(G) * wave_lds_bytes(S); }
+inline size_t lds_for(int G, int S) { return (size_t)waves_for(G, S) * wave_lds_bytes(S); }
 
 int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent) {
-  const int W = (mode == kFused) ? waves_for(G) : 4;
+  const int W = (mode == kFused) ? waves_for(G, S) : 4;
   const int tile = (mode == kFused) ? G : 4;
   a.games_per_tile = tile;
   a.layout = S;
@@ -436,7 +444,10 @@ int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t*
     a.ep_len = ep_len;
     a.ts = timed ? c->ts + 2 * p : nullptr;
     a.tickets = c->tickets + p;
-    int rc = launch_ply(c, s, kFused, a, G, S, true);
+    // without observations a game is short next to a ticket round trip:
+    // take larger chunks
+    const int chunk = obs ? G : (G < 8 ? 8 : G);
+    int rc = launch_ply(c, s, kFused, a, chunk, S, true);
     if (rc != STRATEGO_OK) return rc;
   }
   return STRATEGO_OK;
@@ -479,6 +490,8 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; return STRATEGO_E_HIP; }
   c->num_cu = prop.multiProcessorCount;
   c->max_lds = prop.sharedMemPerBlock;
+  g_max_lds = c->max_lds;
+  if (lds_for(G, S) > c->max_lds) { delete c; return STRATEGO_E_INVAL; }
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0)
     khz = 100000;
@@ -906,7 +919,7 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
       int per_cu = 0;
       const void* fused = S == kLayoutBits ? reinterpret_cast<const void*>(&k_ply<kFused, true>)
                                            : reinterpret_cast<const void*>(&k_ply<kFused, false>);
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64 * waves_for(G), lds_for(G, S)) !=
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64 * waves_for(G, S), lds_for(G, S)) !=
               hipSuccess ||
           per_cu <= 0)
         continue;

@@ -374,3 +374,32 @@ def test_serving_results_same_alone_and_in_the_mix():
         if kind == E.REQ_STEP:
             assert_same(f"request {r} obs vs oracle", obs_mix_h[f:f + b], rr["obs"])
     eng.close()
+
+
+# ---------------------------------------------------------------- full size
+def test_65536_games_graph_plies_sampled_against_oracle():
+    """The benchmark's configuration (65,536 games, auto-reset, 64-ply hipGraph
+    launches, autotuned tiling): 600 sampled games, checked one by one against
+    the oracle playing only those game ids, on the final records after 128 plies
+    and on the last ply's mask, actions and both observations."""
+    n, seed, P = 65536, 1, 64
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
+    E.stratego_autotune(eng.ctx, eng.obs, eng.mask, plies=2)
+    acts = torch.empty((P, n), dtype=torch.int16, device="cuda")
+    for _ in range(2):
+        E.stratego_run_plies(eng.ctx, P, mask=eng.mask, num_legal=eng.num_legal, actions=acts,
+                             obs=eng.obs, use_graph=True)
+    rng = np.random.default_rng(0)
+    ids = np.sort(rng.choice(n, size=600, replace=False)).astype(np.int64)
+    idx = torch.from_numpy(ids).cuda()
+    ref = O.OracleEngine(len(ids), seed, k_battleless=100, max_moves=1000, auto_reset=True,
+                         game_ids=ids.astype(np.uint32))
+    for p in range(2 * P):
+        r = ref.ply(obs=(p == 2 * P - 1))
+        if p >= P:
+            assert_same(f"actions@{p}", cpu(acts[p - P].index_select(0, idx)), r["actions"])
+    assert_same("last mask", cpu(eng.mask.index_select(0, idx)), r["mask"])
+    assert_same("last obs", cpu(eng.obs.index_select(0, idx)), r["obs"])
+    assert_same("records", cpu(eng.export().index_select(0, idx)), ref.export())
+    assert eng.error() == (0, -1)
+    eng.close()
