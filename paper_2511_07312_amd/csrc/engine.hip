@@ -72,20 +72,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   if (byte_image) clear_lds(slab + kSlabImage, image_bytes_for(a.layout));
   const int G = a.games_per_tile;
   const int ntiles = (a.n + G - 1) / G;
-  // Work distribution.  Persistent launches: each wave takes chunks of G
-  // consecutive games from the ply's ticket counter, in address order, as it
-  // becomes free.  Otherwise: tiles blockIdx.x, +gridDim.x, ...; in a tile,
-  // every W-th game.
+  // Work distribution: every wave works through tiles of G consecutive games
+  // of its own.  With a ticket counter (persistent launches) a wave takes the
+  // next tile in address order whenever it becomes free; otherwise wave w of
+  // workgroup b takes tiles bW+w, bW+w+gridDim.x*W, ...
   const bool dynamic = a.tickets != nullptr;
+  const int workers = gridDim.x * W;
   auto grab = [&]() -> int {
     int t = 0;
     if (lane == 0) t = (int)atomicAdd(a.tickets, 1u);
     return __shfl(t, 0, 64);
   };
-  int tile, gi;
-  if (dynamic) { tile = grab(); gi = 0; }
-  else { tile = blockIdx.x; gi = wave; }
-  const int step_gi = dynamic ? 1 : W;
+  int tile = dynamic ? grab() : (int)blockIdx.x * W + wave;
+  int gi = 0;
   int i = tile < ntiles ? tile * G + gi : a.n;
   bool have = i < a.n;
   int slot = have ? (a.slots ? a.slots[i] : i) : 0;
@@ -94,12 +93,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   int cur = 0;   // offset of the current record buffer: 0 or spare
   while (have) {
     // the next game of this wave (its chunk is grabbed only when needed)
-    int ngi = gi + step_gi, ntile = tile;
+    int ngi = gi + 1, ntile = tile;
     bool need_grab = false;
     if (ngi >= G || tile * G + ngi >= a.n) {
-      ngi = dynamic ? 0 : wave;
+      ngi = 0;
       if (dynamic) need_grab = true;
-      else ntile += gridDim.x;
+      else ntile += workers;
     }
     int inext = a.n;
     bool next_have = false, resolved = false;
@@ -367,15 +366,13 @@ inline int waves_for(int G, int S) {
 // Dynamic LDS of one fused-engine workgroup.
 inline size_t lds_for(int G, int S) { return (size_t)waves_for(G, S) * wave_lds_bytes(S); }
 
-int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent) {
+// grow: observation-free plies, where a game is short next to a ticket round
+// trip; the tile grows up to 8 games while every wave still gets two or more.
+int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent,
+               bool grow = false) {
   const int W = (mode == kFused) ? waves_for(G, S) : 4;
-  const int tile = (mode == kFused) ? G : 4;
-  a.games_per_tile = tile;
-  a.layout = S;
   const size_t lds = (size_t)W * wave_lds_bytes(S);
   if (lds > c->max_lds) return STRATEGO_E_INVAL;
-  int ntiles = grid_for(a.n, tile);
-  int grid = ntiles;
   const bool bits = S == kLayoutBits;
   const void* fn = nullptr;
   switch (mode) {
@@ -393,13 +390,22 @@ int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S
       break;
     default: return STRATEGO_E_INVAL;
   }
+  int cap = INT_MAX;
   if (persistent) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * W, lds) != hipSuccess || per_cu <= 0)
       return STRATEGO_E_INVAL;
-    int cap = per_cu * c->num_cu;
-    if (grid > cap) grid = cap;
+    cap = per_cu * c->num_cu;
   }
+  int tile = (mode == kFused) ? G : 1;
+  if (persistent && grow) {
+    const int64_t waves = (int64_t)cap * W;
+    while (tile < 8 && (int64_t)a.n >= 2 * waves * (2 * tile)) tile *= 2;
+  }
+  a.games_per_tile = tile;
+  a.layout = S;
+  int grid = grid_for(grid_for(a.n, tile), W);
+  if (grid > cap) grid = cap;
   if (grid <= 0) return STRATEGO_OK;
   void* args[] = {&a};
   if (hipLaunchKernel(fn, dim3(grid), dim3(64 * W), args, lds, s) != hipSuccess) return STRATEGO_E_HIP;
@@ -444,10 +450,7 @@ int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t*
     a.ep_len = ep_len;
     a.ts = timed ? c->ts + 2 * p : nullptr;
     a.tickets = c->tickets + p;
-    // without observations a game is short next to a ticket round trip:
-    // take larger chunks
-    const int chunk = obs ? G : (G < 8 ? 8 : G);
-    int rc = launch_ply(c, s, kFused, a, chunk, S, true);
+    int rc = launch_ply(c, s, kFused, a, G, S, true, obs == nullptr);
     if (rc != STRATEGO_OK) return rc;
   }
   return STRATEGO_OK;
