@@ -19,3 +19,4 @@ from .oracle import (  # noqa: F401
     MASK_WORDS,
     NCHAN,
 )
+from .history import OracleRolloutBuffer, WindowError  # noqa: F401,E402
