@@ -51,11 +51,13 @@ extern "C" {
 #define STRATEGO_E_HIP (-3)            /* a HIP runtime call failed */
 #define STRATEGO_E_ILLEGAL_ACTION (-4) /* a live game received an illegal action */
 #define STRATEGO_E_BAD_STATE (-5)      /* an imported record is malformed */
+#define STRATEGO_E_RANGE (-6)          /* time step outside the rollout buffer's window */
 
 #define STRATEGO_NUM_CHANNELS 488
 #define STRATEGO_MASK_WORDS 157
 #define STRATEGO_RECORD_BYTES 1536
 #define STRATEGO_OBS_BYTES_PER_GAME 97600
+#define STRATEGO_HISTORY_BYTES_PER_GAME_STEP 1544  /* rollout buffer: record + step outcome */
 
 typedef struct stratego_ctx stratego_ctx;
 
@@ -69,7 +71,7 @@ typedef struct {
   int32_t games_per_wg;   /* fused engine tile size G in {1,2,4,8,16}; 0 = default */
   int32_t lds_layout;     /* observation staging in LDS: 1 = bit planes; 2..6 = byte images in
                              1, 2, 4, 8, 16 channel segments; 0 = default (1) */
-  int32_t reserved;
+  int32_t history_len;    /* rollout buffer: time steps kept (App. B.1), 0..2^20; 0 = none */
 } stratego_config;
 
 /* Create a context with N games, all reset to fresh setups (episode 0).
@@ -213,6 +215,89 @@ int stratego_autotune(stratego_ctx* ctx, uint8_t* obs_dev, uint64_t* mask_dev, i
 /* Current fused-engine tiling (games per workgroup, LDS layout). */
 int stratego_get_tiling(stratego_ctx* ctx, int32_t* games_per_wg, int32_t* lds_layout);
 int stratego_set_tiling(stratego_ctx* ctx, int32_t games_per_wg, int32_t lds_layout);
+
+/* Rollout buffer (App. B.1: the simulator doubles as the rollout buffer; past
+ * legal masks and information states are recomputed on demand from a
+ * circular, preallocated history instead of being stored).
+ *
+ * Time steps count whole-batch plies: t = 0 is the state after init, and each
+ * stratego_step or fused ply of stratego_run_plies maps the states at t to
+ * those at t + 1.  With history_len = H > 0, every such ply records, for each
+ * game, the state the action is applied to (its canonical record) and the
+ * step's outcome, in ring row t mod H; stratego_init allocates H x N x 1544
+ * bytes for this (against 98,856 bytes per game step for storing the mask and
+ * both information states instead).  Queries accept
+ * t in [max(0, T - H), T], T being the current time step, and return E_RANGE
+ * otherwise; t = T reads the live states (resets and imports made since the
+ * last ply included).  With H > 0, stratego_run_plies_slots and
+ * stratego_serve, which step subsets of the games, return E_INVAL.
+ *
+ * Every query takes games_dev: int32[count] game indices (duplicates
+ * allowed), or NULL for games 0..count-1 (count <= N); outputs are indexed by
+ * position in that list.  An index outside [0, N) is skipped and latches
+ * E_BAD_STATE with its list position (stratego_get_error).  count = 0 is a
+ * no-op (outputs may then be NULL).  Queries are asynchronous on the
+ * context's stream. */
+
+/* The query window: *oldest = max(0, T - H), *current = T (either may be NULL). */
+int stratego_history_window(stratego_ctx* ctx, int64_t* oldest, int64_t* current);
+
+/* ComputeLegalActionMask(t) of App. B.1: mask_dev uint64[count][157] and/or
+ * num_legal_dev int16[count] (either may be NULL, not both), as
+ * stratego_legal_mask would have returned at time step t. */
+int stratego_history_legal_mask(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
+                                uint64_t* mask_dev, int16_t* num_legal_dev);
+
+/* ComputeInfostateTensor(t) of App. B.1: obs_dev uint8[count][2][488][10][10],
+ * both players' information states (App. C) at time step t, as
+ * stratego_encode_obs would have returned then. */
+int stratego_history_encode_obs(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
+                                uint8_t* obs_dev);
+
+/* Scalar and per-square queries of App. B.1 at time step t.  Every pointer is a
+ * device array indexed by list position and may be NULL.  "The action at t"
+ * is the one applied to the state at t (none yet at t = T).
+ *   acting_player       int8:  0 red, 1 blue (ActingPlayer)
+ *   played_action       int16: the action at t, -1 at t = T (GetPlayedActions)
+ *   num_moves           int32: moves played in the episode (GetNumMoves)
+ *   moves_since_attack  int32: consecutive moves without a battle
+ *                              (GetNumMovesSinceLastAttack)
+ *   reward_pl0          int8:  outcome for red (+1, 0, -1) if the action at t
+ *                              ended the episode, else 0 (ComputeRewardPl0)
+ *   terminated_since    int32: 0 for a live game; for a finished one, the
+ *                              number of consecutive terminal states up to t in
+ *                              the window (GetTerminatedSince; only games
+ *                              without auto-reset stay finished)
+ *   has_legal_movement  uint8: the acting player has a legal move in a live
+ *                              game (GetHasLegalMovement)
+ *   flag_captured       uint8: the action at t captured a Flag (GetFlagCaptured)
+ *   is_unknown          uint8 [count][100]: 1 on squares holding an opponent
+ *                              piece whose type the acting player has not seen
+ *                              (ComputeIsUnknownPiece), acting player's frame
+ *   piece_onehot        uint8 [count][24][100]: plane k < 12 marks the acting
+ *                              player's pieces of type k, plane 12 + k the
+ *                              opponent's (true types; ComputePieceTypeOnehot),
+ *                              acting player's frame */
+typedef struct {
+  int8_t* acting_player;
+  int16_t* played_action;
+  int32_t* num_moves;
+  int32_t* moves_since_attack;
+  int8_t* reward_pl0;
+  int32_t* terminated_since;
+  uint8_t* has_legal_movement;
+  uint8_t* flag_captured;
+  uint8_t* is_unknown;
+  uint8_t* piece_onehot;
+} stratego_history_outputs;
+int stratego_history_info(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
+                          const stratego_history_outputs* out);
+
+/* Canonical records (1536 bytes each) of the listed games at time step t, to
+ * states_dev uint8[count][1536]: importing them with stratego_reset rewinds
+ * those games to t (App. B.1: capturing past states for search). */
+int stratego_history_export(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
+                            void* states_dev);
 
 /* Synchronise the stream, then report and clear the latched device error:
  * returns STRATEGO_OK, E_ILLEGAL_ACTION or E_BAD_STATE; first_bad_slot (may

@@ -26,6 +26,7 @@ namespace {
 enum : int { kDoMask = 1, kDoSample = 2, kDoEncode = 4, kDoStep = 8, kStepFromInput = 16 };
 constexpr int kFused = kDoMask | kDoSample | kDoEncode | kDoStep;
 constexpr int kMaxTimedPlies = 4096;
+constexpr int kMaxHistory = 1 << 20;
 
 struct PlyArgs {
   uint8_t* states;
@@ -46,10 +47,23 @@ struct PlyArgs {
   int32_t* err;
   unsigned long long* ts;
   unsigned int* tickets;   // this ply's work counter (persistent launches), else NULL
+  // rollout buffer: record and step outcome of every stepped game at
+  // row *hist_slot of the ring (NULL: not recorded)
+  uint8_t* hist;
+  uint64_t* hist_steps;
+  const int32_t* hist_slot;
   Rules rules;
   int32_t games_per_tile;
   int32_t layout;     // observation staging layout in LDS
 };
+
+// Step outcome of one game at one time step of the rollout buffer: action
+// (bits 0-15), done (16-23), outcome (24-31), reason (32-39), ep_len (48-63).
+__device__ __forceinline__ uint64_t pack_step(int action, const StepOut& o) {
+  return (uint64_t)(uint16_t)(int16_t)action | (uint64_t)(uint8_t)o.done << 16 |
+         (uint64_t)(uint8_t)(int8_t)o.outcome << 24 | (uint64_t)(uint8_t)o.reason << 32 |
+         (uint64_t)(uint16_t)(int16_t)o.ep_len << 48;
+}
 
 // Per-wave LDS: the slab of the layout plus a spare record buffer.  While a
 // game is processed, the next game's record is fetched into registers early
@@ -68,6 +82,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   const int spare = slab_bytes_for(a.layout);
   if (a.ts && threadIdx.x == 0) atomicMin(&a.ts[0], (unsigned long long)wall_clock64());
   const bool encode = (MODE & kDoEncode) && a.obs;
+  const size_t hist_row = ((MODE & kDoStep) && a.hist) ? (size_t)(*a.hist_slot) * (size_t)a.total : 0;
   const bool byte_image = encode && a.layout != kLayoutBits;
   if (byte_image) clear_lds(slab + kSlabImage, image_bytes_for(a.layout));
   const int G = a.games_per_tile;
@@ -172,6 +187,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         else encode_game_bytes(R, slab, a.rules, segments_of(a.layout), a.obs + (size_t)oi * kObsPerGame);
       }
       if (MODE & kDoStep) {
+        if (a.hist) store_record(a.hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
         StepOut o = step_game(R, slab + kSlabScratch, a.rules, action);
         if (lane == 0) {
           const size_t row = (size_t)a.out_base + oi;
@@ -180,6 +196,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           if (a.reason) a.reason[row] = (uint8_t)o.reason;
           if (a.ep_len) a.ep_len[row] = (int16_t)o.ep_len;
           if (o.illegal) atomicMin(&a.err[0], slot);
+          if (a.hist) a.hist_steps[hist_row + slot] = pack_step(action, o);
         }
         wave_sync();
         store_record(gstate, R);
@@ -308,6 +325,132 @@ __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Rows of the rollout buffer's ring for the next nplies recorded plies, from
+// the device's time-step counter, which then advances.  A kernel, so that
+// every replay of a captured graph takes fresh rows.
+__global__ void __launch_bounds__(256) k_hist_clock(int64_t* clock, int32_t* rows, int32_t nplies,
+                                                   int32_t H) {
+  const int64_t t = clock[0];
+  for (int p = threadIdx.x; p < nplies; p += blockDim.x) rows[p] = (int32_t)((t + p) % H);
+  __syncthreads();
+  if (threadIdx.x == 0) clock[0] = t + nplies;
+}
+
+// ---------------------------------------------------------------- rollout-buffer queries
+// App. B.1: quantities of a past time step are recomputed from the recorded
+// state instead of being stored.  One wave per listed game.
+enum : int { kQMask = 0, kQObs = 1, kQInfo = 2, kQRecord = 3 };
+
+struct HistArgs {
+  const uint8_t* src;       // records at time step t: a ring row or the live states
+  const uint64_t* steps;    // step outcomes at t (NULL: t is the current step)
+  const uint8_t* ring;      // the whole ring, for walking back over earlier steps
+  int64_t t, oldest;
+  int32_t H, N;
+  const int32_t* games;     // games to query (NULL: 0..count-1)
+  int32_t count;
+  uint64_t* mask;
+  int16_t* num_legal;
+  uint8_t* obs;
+  uint8_t* records;
+  stratego_history_outputs out;
+  int32_t* err;
+  Rules rules;
+};
+
+__host__ __device__ constexpr int hist_lds_bytes(int q) {
+  return q == kQObs ? slab_bytes_for(kLayoutBits)
+       : q == kQMask ? kSlabImage + kDestSetBytes
+       : q == kQInfo ? kRecordBytes : 16;
+}
+
+template <int Q>
+__global__ void __launch_bounds__(256) k_hist(HistArgs h) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (i >= h.count) return;
+  const int g = h.games ? h.games[i] : i;
+  if (g < 0 || g >= h.N) {
+    if (lane == 0) atomicMin(&h.err[1], i);
+    return;
+  }
+  const uint8_t* src = h.src + (size_t)g * kRecordBytes;
+  if (Q == kQRecord) {
+    store_record(h.records + (size_t)i * kRecordBytes, src);
+    return;
+  }
+  uint8_t* slab = smem + wave * hist_lds_bytes(Q);
+  uint8_t* R = slab;
+  load_record(R, src);
+  if (Q == kQMask) {
+    uint64_t w[3];
+    const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
+    if (h.mask) {
+      uint64_t* m = h.mask + (size_t)i * kMaskWords;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (lane + 64 * k < kMaskWords) m[lane + 64 * k] = w[k];
+    }
+    if (h.num_legal && lane == 0) h.num_legal[i] = (int16_t)n;
+  } else if (Q == kQObs) {
+    compute_probq(R, slab);
+    encode_game_bits(R, slab, h.rules, h.obs + (size_t)i * kObsPerGame);
+  } else {
+    const stratego_history_outputs& o = h.out;
+    const int ply = (int)hdr_u32(R, kOffPly), p = ply & 1;
+    const bool done = R[kOffDone] != 0;
+    const bool movable = has_move(R, p) && !done;   // wave-wide
+    // per-square views in the acting player's frame
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int sq = lane + 64 * k;
+      if (sq >= kSquares) break;
+      const int f = p == 0 ? sq : 99 - sq;
+      const int id = board_at(R, sq);
+      int plane = -1;
+      bool unknown = false;
+      if (id >= 0) {
+        const uint32_t w0 = piece_words(R, id)[0];
+        const bool own = owner(id) == p;
+        plane = (own ? 0 : 12) + p_type(w0);
+        unknown = !own && !p_revealed(w0);
+      }
+      if (o.is_unknown) o.is_unknown[(size_t)i * kSquares + f] = (uint8_t)unknown;
+      if (o.piece_onehot)
+        for (int c = 0; c < 24; ++c) o.piece_onehot[((size_t)i * 24 + c) * kSquares + f] = (uint8_t)(c == plane);
+    }
+    if (lane == 0) {
+      int action = -1, sdone = 0, soutcome = 0, sreason = 0;
+      if (h.steps) {
+        const uint64_t e = h.steps[g];
+        action = (int16_t)(e & 0xffffu);
+        sdone = (int)((e >> 16) & 0xffu);
+        soutcome = (int8_t)((e >> 24) & 0xffu);
+        sreason = (int)((e >> 32) & 0xffu);
+      }
+      const bool ended = sdone && !done;   // the action at t ended the episode
+      int since = 0;
+      if (done) {   // steps since the episode ended: the run of terminal states up to t
+        since = 1;
+        for (int64_t u = h.t - 1; u >= h.oldest; --u) {
+          const uint8_t* e = h.ring + ((size_t)(u % h.H) * h.N + g) * kRecordBytes;
+          if (!e[kOffDone]) break;
+          ++since;
+        }
+      }
+      if (o.acting_player) o.acting_player[i] = (int8_t)p;
+      if (o.played_action) o.played_action[i] = (int16_t)action;
+      if (o.num_moves) o.num_moves[i] = ply;
+      if (o.moves_since_attack) o.moves_since_attack[i] = (int32_t)hdr_u32(R, kOffBattleless);
+      if (o.reward_pl0) o.reward_pl0[i] = (int8_t)(ended ? soutcome : 0);
+      if (o.terminated_since) o.terminated_since[i] = since;
+      if (o.has_legal_movement) o.has_legal_movement[i] = (uint8_t)movable;
+      if (o.flag_captured) o.flag_captured[i] = (uint8_t)(ended && sreason == kReasonFlag);
+    }
+  }
+}
+
 struct GraphEntry {
   int32_t nplies, G, S;
   const void* ptrs[9];
@@ -334,6 +477,13 @@ struct stratego_ctx {
   int64_t steps;
   int G, S;
   std::vector<GraphEntry> graphs;
+  // rollout buffer (App. B.1): H time steps of N records and step outcomes
+  int64_t t;               // whole-batch plies recorded so far (the current time step)
+  int32_t H;
+  uint8_t* hist;           // [H][N] canonical records
+  uint64_t* hist_steps;    // [H][N]
+  int64_t* hist_clock;     // device copy of t
+  int32_t* hist_rows;      // ring rows of the plies of one enqueue
 };
 
 namespace {
@@ -423,10 +573,29 @@ PlyArgs base_args(stratego_ctx* c) {
   return a;
 }
 
+// Ring rows for the next nplies recorded plies (no-op without a rollout buffer).
+int enqueue_hist_clock(stratego_ctx* c, hipStream_t s, int32_t nplies) {
+  if (!c->hist) return STRATEGO_OK;
+  hipLaunchKernelGGL(k_hist_clock, dim3(1), dim3(256), 0, s, c->hist_clock, c->hist_rows, nplies, c->H);
+  return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+void set_hist(stratego_ctx* c, PlyArgs& a, int p) {
+  if (!c->hist) return;
+  a.hist = c->hist;
+  a.hist_steps = c->hist_steps;
+  a.hist_slot = c->hist_rows + p;
+}
+
 int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t* slots, int32_t n,
                   uint64_t* mask, int16_t* num_legal, int16_t* actions, uint8_t* obs, int8_t* done,
-                  int8_t* outcome, uint8_t* reason, int16_t* ep_len, bool timed, int G, int S) {
+                  int8_t* outcome, uint8_t* reason, int16_t* ep_len, bool timed, int G, int S,
+                  bool record) {
   if (nplies > kMaxTimedPlies) return STRATEGO_E_INVAL;
+  if (record) {
+    int rc = enqueue_hist_clock(c, s, nplies);
+    if (rc != STRATEGO_OK) return rc;
+  }
   // zero the per-ply work counters (a kernel, so the step can sit in a graph)
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nplies, 256)), dim3(256), 0, s,
                      reinterpret_cast<int32_t*>(c->tickets), nplies, 0);
@@ -450,6 +619,7 @@ int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t*
     a.ep_len = ep_len;
     a.ts = timed ? c->ts + 2 * p : nullptr;
     a.tickets = c->tickets + p;
+    if (record) set_hist(c, a, p);
     int rc = launch_ply(c, s, kFused, a, G, S, true, obs == nullptr);
     if (rc != STRATEGO_OK) return rc;
   }
@@ -468,6 +638,7 @@ const char* stratego_strerror(int code) {
     case STRATEGO_E_HIP: return "HIP runtime error";
     case STRATEGO_E_ILLEGAL_ACTION: return "illegal action for a live game";
     case STRATEGO_E_BAD_STATE: return "malformed state record";
+    case STRATEGO_E_RANGE: return "time step outside the rollout buffer's window";
     default: return "unknown error";
   }
 }
@@ -481,6 +652,7 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
   int G = cfg->games_per_wg ? cfg->games_per_wg : 1;
   int S = cfg->lds_layout ? cfg->lds_layout : kLayoutBits;
   if (!valid_tiling(G, S)) return STRATEGO_E_INVAL;
+  if (cfg->history_len < 0 || cfg->history_len > kMaxHistory) return STRATEGO_E_INVAL;
   stratego_ctx* c = new (std::nothrow) stratego_ctx();
   if (!c) return STRATEGO_E_NOMEM;
   c->cfg = *cfg;
@@ -535,6 +707,21 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
     stratego_destroy(c);
     return STRATEGO_E_NOMEM;
   }
+  if (cfg->history_len > 0) {
+    c->H = cfg->history_len;
+    const size_t rows = (size_t)c->H * (size_t)cfg->num_games;
+    auto alloc = [](auto** p, size_t bytes) {
+      if (hipMalloc(reinterpret_cast<void**>(p), bytes) == hipSuccess) return true;
+      *p = nullptr;
+      return false;
+    };
+    if (!alloc(&c->hist, rows * kRecordBytes) || !alloc(&c->hist_steps, rows * sizeof(uint64_t)) ||
+        !alloc(&c->hist_clock, sizeof(int64_t)) || !alloc(&c->hist_rows, sizeof(int32_t) * kMaxTimedPlies)) {
+      stratego_destroy(c);
+      return STRATEGO_E_NOMEM;
+    }
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int32_t*>(c->hist_clock), 2, 0);
+  }
   // kernels whose dynamic LDS may exceed the default limit
   const void* big_lds[] = {reinterpret_cast<const void*>(&k_ply<kFused, true>),
                            reinterpret_cast<const void*>(&k_ply<kFused, false>),
@@ -588,9 +775,14 @@ int stratego_step(stratego_ctx* c, const int16_t* actions, int8_t* done, int8_t*
   a.outcome = outcome;
   a.reason = reason;
   a.ep_len = ep_len;
-  int rc = launch_ply(c, c->stream, kDoStep | kStepFromInput, a, 4, 6, false);
-  if (rc == STRATEGO_OK) c->steps += c->cfg.num_games;
-  return rc;
+  int rc = enqueue_hist_clock(c, c->stream, 1);
+  if (rc != STRATEGO_OK) return rc;
+  set_hist(c, a, 0);
+  rc = launch_ply(c, c->stream, kDoStep | kStepFromInput, a, 4, 6, false);
+  if (rc != STRATEGO_OK) return rc;
+  c->steps += c->cfg.num_games;
+  c->t += 1;
+  return STRATEGO_OK;
 }
 
 int stratego_encode_obs(stratego_ctx* c, uint8_t* obs) {
@@ -623,7 +815,7 @@ int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t*
       int rc = enqueue_plies(c, c->stream, np, nullptr, n, mask, num_legal, actions ? actions + off : nullptr,
                              obs, done ? done + off : nullptr, outcome ? outcome + off : nullptr,
                              reason ? reason + off : nullptr, ep_len ? ep_len + off : nullptr, timed, c->G,
-                             c->S);
+                             c->S, true);
       if (rc != STRATEGO_OK) return rc;
     }
   } else {
@@ -642,7 +834,7 @@ int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t*
       if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
         return STRATEGO_E_HIP;
       int rc = enqueue_plies(c, c->capture_stream, nplies, nullptr, n, mask, num_legal, actions, obs,
-                             done, outcome, reason, ep_len, timed, c->G, c->S);
+                             done, outcome, reason, ep_len, timed, c->G, c->S, true);
       hipError_t ec = hipStreamEndCapture(c->capture_stream, &graph);
       if (rc != STRATEGO_OK) { if (ec == hipSuccess) (void)hipGraphDestroy(graph); return rc; }
       if (ec != hipSuccess) return STRATEGO_E_HIP;
@@ -671,6 +863,7 @@ int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t*
     if (hipGetLastError() != hipSuccess) return STRATEGO_E_HIP;
   }
   c->steps += (int64_t)nplies * n;
+  c->t += nplies;
   return STRATEGO_OK;
 }
 
@@ -678,13 +871,15 @@ int stratego_run_plies_slots(stratego_ctx* c, const int32_t* slots, int32_t nslo
                              uint64_t* mask, int16_t* actions, uint8_t* obs, int8_t* done,
                              int8_t* outcome, uint8_t* reason, int16_t* ep_len) {
   if (!c || !slots || nslots < 0 || nslots > c->cfg.num_games || nplies < 0) return STRATEGO_E_INVAL;
+  if (c->hist) return STRATEGO_E_INVAL;   // the rollout buffer indexes whole-batch plies
   if (nslots == 0 || nplies == 0) return STRATEGO_OK;
   for (int32_t p0 = 0; p0 < nplies; p0 += kMaxTimedPlies) {
     const int32_t np = nplies - p0 < kMaxTimedPlies ? nplies - p0 : kMaxTimedPlies;
     const size_t off = (size_t)p0 * nslots;
     int rc = enqueue_plies(c, c->stream, np, slots, nslots, mask, nullptr, actions ? actions + off : nullptr,
                            obs, done ? done + off : nullptr, outcome ? outcome + off : nullptr,
-                           reason ? reason + off : nullptr, ep_len ? ep_len + off : nullptr, false, c->G, c->S);
+                           reason ? reason + off : nullptr, ep_len ? ep_len + off : nullptr, false, c->G, c->S,
+                           false);
     if (rc != STRATEGO_OK) return rc;
   }
   c->steps += (int64_t)nplies * nslots;
@@ -706,6 +901,7 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
                    int32_t realtime, stratego_request_result* results, stratego_serve_stats* stats) {
   if (!c || nreq < 0 || (nreq > 0 && (!reqs || !in_states || !out_states || !results)))
     return STRATEGO_E_INVAL;
+  if (c->hist) return STRATEGO_E_INVAL;   // the rollout buffer indexes whole-batch plies
   const int N = c->cfg.num_games;
   bool any_step = false;
   for (int r = 0; r < nreq; ++r) {
@@ -928,11 +1124,11 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
         continue;
       // warm-up ply, then the timed plies
       rc = enqueue_plies(c, c->stream, 1, nullptr, n, mask, nullptr, nullptr, obs, nullptr, nullptr, nullptr,
-                         nullptr, false, G, S);
+                         nullptr, false, G, S, false);
       if (rc != STRATEGO_OK) break;
       (void)hipEventRecord(e0, c->stream);
       rc = enqueue_plies(c, c->stream, plies, nullptr, n, mask, nullptr, nullptr, obs, nullptr, nullptr,
-                         nullptr, nullptr, false, G, S);
+                         nullptr, nullptr, false, G, S, false);
       (void)hipEventRecord(e1, c->stream);
       if (hipEventSynchronize(e1) != hipSuccess) { rc = STRATEGO_E_HIP; break; }
       float ms = 0.f;
@@ -956,6 +1152,105 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
   c->S = best_S;
   if (n_entries) *n_entries = count;
   return STRATEGO_OK;
+}
+
+int stratego_history_window(stratego_ctx* c, int64_t* oldest, int64_t* current) {
+  if (!c) return STRATEGO_E_INVAL;
+  if (oldest) *oldest = c->t - c->H > 0 ? c->t - c->H : 0;
+  if (current) *current = c->t;
+  return STRATEGO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Arguments of a query at time step t, or E_RANGE outside the window.
+int hist_args(stratego_ctx* c, int64_t t, const int32_t* games, int32_t count, HistArgs& h) {
+  std::memset(&h, 0, sizeof(h));
+  if (count < 0 || (!games && count > c->cfg.num_games)) return STRATEGO_E_INVAL;
+  const int64_t T = c->t, oldest = T - c->H > 0 ? T - c->H : 0;
+  if (t < oldest || t > T) return STRATEGO_E_RANGE;
+  const int N = c->cfg.num_games;
+  h.t = t;
+  h.oldest = oldest;
+  h.H = c->H;
+  h.N = N;
+  h.ring = c->hist;
+  h.games = games;
+  h.count = count;
+  h.err = c->err;
+  h.rules = rules_of(c);
+  if (t == T) {
+    h.src = c->states;
+  } else {
+    const size_t row = (size_t)(t % c->H) * (size_t)N;
+    h.src = c->hist + row * kRecordBytes;
+    h.steps = c->hist_steps + row;
+  }
+  return STRATEGO_OK;
+}
+
+int launch_hist(stratego_ctx* c, int q, HistArgs& h) {
+  if (h.count == 0) return STRATEGO_OK;
+  const void* fn = q == kQMask ? reinterpret_cast<const void*>(&k_hist<kQMask>)
+                 : q == kQObs ? reinterpret_cast<const void*>(&k_hist<kQObs>)
+                 : q == kQInfo ? reinterpret_cast<const void*>(&k_hist<kQInfo>)
+                 : reinterpret_cast<const void*>(&k_hist<kQRecord>);
+  void* args[] = {&h};
+  if (hipLaunchKernel(fn, dim3(grid_for(h.count, 4)), dim3(256), args, 4 * hist_lds_bytes(q), c->stream) !=
+      hipSuccess)
+    return STRATEGO_E_HIP;
+  return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stratego_history_legal_mask(stratego_ctx* c, int64_t t, const int32_t* games, int32_t count,
+                                uint64_t* mask, int16_t* num_legal) {
+  if (!c) return STRATEGO_E_INVAL;
+  HistArgs h;
+  int rc = hist_args(c, t, games, count, h);
+  if (rc != STRATEGO_OK || count == 0) return rc;
+  if (!mask && !num_legal) return STRATEGO_E_INVAL;
+  h.mask = mask;
+  h.num_legal = num_legal;
+  return launch_hist(c, kQMask, h);
+}
+
+int stratego_history_encode_obs(stratego_ctx* c, int64_t t, const int32_t* games, int32_t count,
+                                uint8_t* obs) {
+  if (!c) return STRATEGO_E_INVAL;
+  HistArgs h;
+  int rc = hist_args(c, t, games, count, h);
+  if (rc != STRATEGO_OK || count == 0) return rc;
+  if (!obs) return STRATEGO_E_INVAL;
+  h.obs = obs;
+  return launch_hist(c, kQObs, h);
+}
+
+int stratego_history_info(stratego_ctx* c, int64_t t, const int32_t* games, int32_t count,
+                          const stratego_history_outputs* out) {
+  if (!c) return STRATEGO_E_INVAL;
+  HistArgs h;
+  int rc = hist_args(c, t, games, count, h);
+  if (rc != STRATEGO_OK || count == 0) return rc;
+  if (!out) return STRATEGO_E_INVAL;
+  h.out = *out;
+  return launch_hist(c, kQInfo, h);
+}
+
+int stratego_history_export(stratego_ctx* c, int64_t t, const int32_t* games, int32_t count,
+                            void* states) {
+  if (!c) return STRATEGO_E_INVAL;
+  HistArgs h;
+  int rc = hist_args(c, t, games, count, h);
+  if (rc != STRATEGO_OK || count == 0) return rc;
+  if (!states) return STRATEGO_E_INVAL;
+  h.records = reinterpret_cast<uint8_t*>(states);
+  return launch_hist(c, kQRecord, h);
 }
 
 int stratego_get_error(stratego_ctx* c, int32_t* first_bad_slot) {
@@ -988,6 +1283,10 @@ int stratego_destroy(stratego_ctx* c) {
   if (c->tickets) (void)hipFree(c->tickets);
   if (c->srv_dev) (void)hipFree(c->srv_dev);
   if (c->srv_host) (void)hipHostFree(c->srv_host);
+  if (c->hist) (void)hipFree(c->hist);
+  if (c->hist_steps) (void)hipFree(c->hist_steps);
+  if (c->hist_clock) (void)hipFree(c->hist_clock);
+  if (c->hist_rows) (void)hipFree(c->hist_rows);
   (void)hipFree(c->states);
   (void)hipFree(c->backup);
   (void)hipFree(c->err);

@@ -19,17 +19,21 @@ E_NOMEM = -2
 E_HIP = -3
 E_ILLEGAL_ACTION = -4
 E_BAD_STATE = -5
+E_RANGE = -6
 NUM_CHANNELS = 488
 MASK_WORDS = 157
 RECORD_BYTES = 1536
 OBS_BYTES_PER_GAME = 97600
+HISTORY_BYTES_PER_GAME_STEP = 1544
 
 FUNCTIONS = [
     "stratego_init", "stratego_reset", "stratego_legal_mask", "stratego_sample_actions",
     "stratego_step", "stratego_encode_obs", "stratego_export_states", "stratego_run_plies",
     "stratego_run_plies_slots", "stratego_reset_resampled", "stratego_autotune",
     "stratego_get_tiling", "stratego_set_tiling", "stratego_get_error", "stratego_current_step",
-    "stratego_destroy", "stratego_strerror", "stratego_serve",
+    "stratego_destroy", "stratego_strerror", "stratego_serve", "stratego_history_window",
+    "stratego_history_legal_mask", "stratego_history_encode_obs", "stratego_history_info",
+    "stratego_history_export",
 ]
 REQ_STEP = 0
 REQ_ROLLOUT = 1
@@ -40,7 +44,23 @@ class StrategoConfig(ctypes.Structure):
                 ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("game_id_base", ctypes.c_uint32),
                 ("games_per_wg", ctypes.c_int32), ("lds_layout", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32)]
+
+
+class HistoryOutputs(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in (
+        "acting_player", "played_action", "num_moves", "moves_since_attack", "reward_pl0",
+        "terminated_since", "has_legal_movement", "flag_captured", "is_unknown", "piece_onehot")]
+
+
+# dtype and elements per listed game of each history_info output
+HISTORY_INFO = {
+    "acting_player": (torch.int8, 1), "played_action": (torch.int16, 1),
+    "num_moves": (torch.int32, 1), "moves_since_attack": (torch.int32, 1),
+    "reward_pl0": (torch.int8, 1), "terminated_since": (torch.int32, 1),
+    "has_legal_movement": (torch.uint8, 1), "flag_captured": (torch.uint8, 1),
+    "is_unknown": (torch.uint8, 100), "piece_onehot": (torch.uint8, 2400),
+}
 
 
 class TuneEntry(ctypes.Structure):
@@ -100,6 +120,11 @@ def load_library(path=LIB_PATH):
     L.stratego_destroy.argtypes = [P]
     L.stratego_serve.argtypes = [P, ctypes.POINTER(Request), I32, P, P, P, I32, I64, I32,
                                  ctypes.POINTER(RequestResult), ctypes.POINTER(ServeStats)]
+    L.stratego_history_window.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    L.stratego_history_legal_mask.argtypes = [P, I64, P, I32, P, P]
+    L.stratego_history_encode_obs.argtypes = [P, I64, P, I32, P]
+    L.stratego_history_info.argtypes = [P, I64, P, I32, ctypes.POINTER(HistoryOutputs)]
+    L.stratego_history_export.argtypes = [P, I64, P, I32, P]
     L.stratego_strerror.argtypes = [ctypes.c_int]
     L.stratego_strerror.restype = ctypes.c_char_p
     for f in FUNCTIONS:
@@ -138,9 +163,10 @@ def _stream():
 
 # ------------------------------------------------------------------ C-ABI mirrors
 def stratego_init(num_games, seed, k_battleless=100, max_moves=4000, auto_reset=False,
-                  game_id_base=0, games_per_wg=0, lds_layout=0):
+                  game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0):
     cfg = StrategoConfig(int(num_games), int(k_battleless), int(max_moves), int(bool(auto_reset)),
-                         int(seed), int(game_id_base), int(games_per_wg), int(lds_layout), 0)
+                         int(seed), int(game_id_base), int(games_per_wg), int(lds_layout),
+                         int(history_len))
     ctx = ctypes.c_void_p()
     _check(load_library().stratego_init(ctypes.byref(cfg), _stream(), ctypes.byref(ctx)),
            "stratego_init")
@@ -189,6 +215,57 @@ def stratego_export_states(ctx, states):
     n = _num_games(ctx)
     _check(load_library().stratego_export_states(
         ctx, _ptr(states, torch.uint8, n and n * RECORD_BYTES, "states")), "stratego_export_states")
+
+
+def _listed(games, count):
+    if games is None:
+        if count is None:
+            raise ValueError("count is required when games is None")
+        return int(count)
+    return int(games.numel()) if count is None else int(count)
+
+
+def stratego_history_window(ctx):
+    """Returns (oldest, current) time steps of the rollout buffer."""
+    lo, cur = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().stratego_history_window(ctx, ctypes.byref(lo), ctypes.byref(cur)),
+           "stratego_history_window")
+    return lo.value, cur.value
+
+
+def stratego_history_legal_mask(ctx, t, mask=None, num_legal=None, games=None, count=None):
+    m = _listed(games, count)
+    _check(load_library().stratego_history_legal_mask(
+        ctx, int(t), _ptr(games, torch.int32, m, "games"), m,
+        _ptr(mask, torch.int64, m * MASK_WORDS, "mask"), _ptr(num_legal, torch.int16, m, "num_legal")),
+        "stratego_history_legal_mask")
+
+
+def stratego_history_encode_obs(ctx, t, obs, games=None, count=None):
+    m = _listed(games, count)
+    _check(load_library().stratego_history_encode_obs(
+        ctx, int(t), _ptr(games, torch.int32, m, "games"), m,
+        _ptr(obs, torch.uint8, m * OBS_BYTES_PER_GAME, "obs")), "stratego_history_encode_obs")
+
+
+def stratego_history_info(ctx, t, games=None, count=None, **outputs):
+    """outputs: any of the HISTORY_INFO names mapped to GPU tensors."""
+    m = _listed(games, count)
+    out = HistoryOutputs()
+    for name, tensor in outputs.items():
+        if name not in HISTORY_INFO:
+            raise TypeError(f"unknown history output {name}")
+        dtype, per = HISTORY_INFO[name]
+        setattr(out, name, _ptr(tensor, dtype, m * per, name))
+    _check(load_library().stratego_history_info(ctx, int(t), _ptr(games, torch.int32, m, "games"), m,
+                                                ctypes.byref(out)), "stratego_history_info")
+
+
+def stratego_history_export(ctx, t, states, games=None, count=None):
+    m = _listed(games, count)
+    _check(load_library().stratego_history_export(
+        ctx, int(t), _ptr(games, torch.int32, m, "games"), m,
+        _ptr(states, torch.uint8, m * RECORD_BYTES, "states")), "stratego_history_export")
 
 
 def _num_games(ctx):
@@ -296,11 +373,11 @@ class Engine:
     """N games on the current GPU with preallocated output tensors."""
 
     def __init__(self, num_games, seed, k_battleless=100, max_moves=1000, auto_reset=False,
-                 game_id_base=0, games_per_wg=0, lds_layout=0, device="cuda"):
+                 game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, device="cuda"):
         self.n = int(num_games)
         self.device = torch.device(device)
         self.ctx = stratego_init(num_games, seed, k_battleless, max_moves, auto_reset,
-                                 game_id_base, games_per_wg, lds_layout)
+                                 game_id_base, games_per_wg, lds_layout, history_len)
         n, d = self.n, self.device
         self.mask = torch.empty((n, MASK_WORDS), dtype=torch.int64, device=d)
         self.num_legal = torch.empty(n, dtype=torch.int16, device=d)
@@ -348,6 +425,41 @@ class Engine:
 
     def error(self):
         return stratego_get_error(self.ctx)
+
+    # rollout-buffer queries (App. B.1)
+    def window(self):
+        return stratego_history_window(self.ctx)
+
+    def _list(self, games):
+        return self.n if games is None else int(games.numel())
+
+    def mask_at(self, t, games=None):
+        m = self._list(games)
+        mask = torch.empty((m, MASK_WORDS), dtype=torch.int64, device=self.device)
+        nl = torch.empty(m, dtype=torch.int16, device=self.device)
+        stratego_history_legal_mask(self.ctx, t, mask, nl, games, m)
+        return mask, nl
+
+    def obs_at(self, t, games=None, out=None):
+        m = self._list(games)
+        if out is None:
+            out = torch.empty((m, 2, NUM_CHANNELS, 10, 10), dtype=torch.uint8, device=self.device)
+        stratego_history_encode_obs(self.ctx, t, out, games, m)
+        return out
+
+    def info_at(self, t, games=None):
+        m = self._list(games)
+        outs = {name: torch.empty((m, per) if per > 1 else (m,), dtype=dtype, device=self.device)
+                for name, (dtype, per) in HISTORY_INFO.items()}
+        stratego_history_info(self.ctx, t, games, m, **outs)
+        outs["piece_onehot"] = outs["piece_onehot"].view(m, 24, 100)
+        return outs
+
+    def export_at(self, t, games=None):
+        m = self._list(games)
+        out = torch.empty((m, RECORD_BYTES), dtype=torch.uint8, device=self.device)
+        stratego_history_export(self.ctx, t, out, games, m)
+        return out
 
     def close(self):
         if self.ctx is not None:
