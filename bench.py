@@ -9,8 +9,9 @@ synthetic: uniform random setups from the seed and uniform random legal play.
 
 Prints one JSON line.  Also reports per-ply p50/p99 latency (device
 timestamps), the HBM roofline fraction of the fused ply kernel, the plain
-per-call engine at the same size, the autotuner table and the CPU oracle
-timed on a bounded sample of the same workload.
+per-call engine at the same size, serving under load, the rollout buffer
+(recording plies and queries at past steps), the autotuner table and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -150,6 +151,70 @@ def serving_bench(E, torch, n_requests=240, seed=4):
                 pool_slots=slots, rates=out_rates)
 
 
+def rollout_buffer_bench(E, torch, n=GAMES, H=64, warm=256):
+    """Rollout-buffer mode (App. B.1): plies without observations record each
+    game's state in a ring of H steps; masks and information states of past
+    steps are re-materialised on demand.  Times recording plies (against the
+    same plies without a ring) and the queries at a past step, all N games."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps):
+        fn()
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        ev[1].synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    res = {}
+    for hl in (0, H):
+        eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True, history_len=hl)
+        acts = torch.empty((GRAPH_PLIES, n), dtype=torch.int16, device="cuda")
+        done = torch.empty((GRAPH_PLIES, n), dtype=torch.int8, device="cuda")
+        outc = torch.empty((GRAPH_PLIES, n), dtype=torch.int8, device="cuda")
+
+        def plies():
+            E.stratego_run_plies(eng.ctx, GRAPH_PLIES, actions=acts, done=done, outcome=outc,
+                                 use_graph=True)
+        for _ in range(warm // GRAPH_PLIES):
+            plies()
+        res[hl] = timed(plies, 4) / GRAPH_PLIES
+        if hl:
+            lo, T = eng.window()
+            t = T - H // 2
+            obs = torch.empty((n, 2, 488, 10, 10), dtype=torch.uint8, device="cuda")
+            mask = torch.empty((n, 157), dtype=torch.int64, device="cuda")
+            nl = torch.empty(n, dtype=torch.int16, device="cuda")
+            info = {k: torch.empty(n * per, dtype=dt, device="cuda") for k, (dt, per) in E.HISTORY_INFO.items()
+                    if per == 1}
+            obs_ms = timed(lambda: E.stratego_history_encode_obs(eng.ctx, t, obs, None, n), 8)
+            mask_ms = timed(lambda: E.stratego_history_legal_mask(eng.ctx, t, mask, nl, None, n), 8)
+            info_ms = timed(lambda: E.stratego_history_info(eng.ctx, t, None, n, **info), 8)
+            assert eng.error() == (0, -1)
+            del obs, mask, nl, info
+        eng.close()
+        torch.cuda.empty_cache()
+    q_bytes = (97600 + 1536) * n
+    out = dict(
+        games=n, history_len=H,
+        ring_bytes=H * n * 1544,
+        stored_equivalent_bytes=H * n * (97600 + 1256),
+        record_ply_ms=res[H], plain_ply_ms=res[0],
+        recording_overhead=res[H] / res[0] - 1.0,
+        record_game_steps_per_s=n / (res[H] / 1e3),
+        obs_query_ms=obs_ms, obs_query_games_per_s=n / (obs_ms / 1e3),
+        obs_query_roofline=dict(bound="hbm", achieved=q_bytes / (obs_ms / 1e3) / 1e9, peak=HBM_PEAK_GBS,
+                                unit="GB/s", frac=q_bytes / (obs_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                bytes_per_game=97600 + 1536, kernel="k_hist<1> (information states at t)"),
+        mask_query_ms=mask_ms, info_query_ms=info_ms,
+        query_step="t = current - H/2 (a ring row, not the live states)",
+    )
+    print(f"[bench] rollout buffer: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +225,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-history", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--tiling", default=None,
@@ -269,6 +335,7 @@ def main():
     torch.cuda.empty_cache()
     serving = None if args.no_serving else serving_bench(E, torch)
     torch.cuda.empty_cache()
+    rollout_buffer = None if args.no_history else rollout_buffer_bench(E, torch, n)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -304,6 +371,7 @@ def main():
         },
         "plain_engine": plain,
         "serving": serving,
+        "rollout_buffer": rollout_buffer,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }
