@@ -80,7 +80,8 @@ class OracleRolloutBuffer:
         rec = self.records_at(t, games)
         cfg = self.e.cfg
         return OracleEngine.from_records(rec, cfg.seed, k_battleless=cfg.k_battleless,
-                                         max_moves=cfg.max_moves, auto_reset=bool(cfg.auto_reset))
+                                         max_moves=cfg.max_moves, auto_reset=bool(cfg.auto_reset),
+                                         two_square=bool(cfg.two_square))
 
     def mask_at(self, t, games=None):
         return self._engine_at(t, games).mask()
@@ -101,6 +102,7 @@ class OracleRolloutBuffer:
                    num_moves=np.zeros(m, np.int32), moves_since_attack=np.zeros(m, np.int32),
                    reward_pl0=np.zeros(m, np.int8), terminated_since=np.zeros(m, np.int32),
                    has_legal_movement=np.zeros(m, np.uint8), flag_captured=np.zeros(m, np.uint8),
+                   two_square_applies=np.zeros(m, np.uint8),
                    is_unknown=np.zeros((m, 100), np.uint8), piece_onehot=np.zeros((m, 24, 100), np.uint8))
         row = self.rows.get(t) if t < self.t else None
         for k, g in enumerate(ids):
@@ -124,6 +126,7 @@ class OracleRolloutBuffer:
                     u -= 1
                 out["terminated_since"][k] = since
             out["has_legal_movement"][k] = int((not done) and eng.has_legal_move(k, p))
+            out["two_square_applies"][k] = int(eng.two_square_applies(k))
             for s in range(100):
                 pid = int(r[_BOARD + s])   # int8 in the record: >= 128 means empty or lake
                 if pid >= 128:

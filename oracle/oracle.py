@@ -28,7 +28,7 @@ def build(force=True):
 class _Cfg(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("k_battleless", ctypes.c_int32),
                 ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("two_square", ctypes.c_int32)]
 
 
 _lib = None
@@ -46,7 +46,7 @@ def lib():
         P = ctypes.c_void_p
         L.orc_state_bytes.restype = ctypes.c_size_t
         L.orc_batch_reset.argtypes = [P, ctypes.c_int, P, P]
-        L.orc_batch_mask.argtypes = [P, ctypes.c_int, P, P]
+        L.orc_batch_mask.argtypes = [P, ctypes.c_int, P, P, P]
         L.orc_batch_sample.argtypes = [P, ctypes.c_int, P, P, P, P]
         L.orc_batch_step.argtypes = [P, ctypes.c_int, P, P, P, P, P, P]
         L.orc_batch_step.restype = ctypes.c_int
@@ -57,10 +57,12 @@ def lib():
         L.orc_batch_resample.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                          ctypes.c_uint32, P]
         L.orc_batch_ply.argtypes = [P, ctypes.c_int, P, P, P, P, P, P, P, P, P]
-        L.orc_legal_list.argtypes = [P, ctypes.c_int, P]
+        L.orc_legal_list.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
         L.orc_legal_list.restype = ctypes.c_int
-        L.orc_has_legal_move.argtypes = [P, ctypes.c_int]
+        L.orc_has_legal_move.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.orc_has_legal_move.restype = ctypes.c_int
+        L.orc_two_square_applies.argtypes = [P, P]
+        L.orc_two_square_applies.restype = ctypes.c_int
         L.orc_terminal_check.argtypes = [P, P]
         L.orc_battle.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_battle.restype = ctypes.c_int
@@ -119,12 +121,12 @@ class OracleEngine:
     """N independent games advanced by the C oracle."""
 
     def __init__(self, n, seed, k_battleless=100, max_moves=1000, auto_reset=False,
-                 game_ids=None, reset=True):
+                 game_ids=None, reset=True, two_square=False):
         L = lib()
         self.n = int(n)
         self.sb = int(L.orc_state_bytes())
         self.states = np.zeros(self.n * self.sb, dtype=np.uint8)
-        self.cfg = _Cfg(seed, k_battleless, max_moves, 1 if auto_reset else 0, 0)
+        self.cfg = _Cfg(seed, k_battleless, max_moves, 1 if auto_reset else 0, 1 if two_square else 0)
         if reset:
             self.reset(game_ids)
 
@@ -144,7 +146,7 @@ class OracleEngine:
     def mask(self):
         m = np.zeros((self.n, MASK_WORDS), dtype=np.uint64)
         nl = np.zeros(self.n, dtype=np.int16)
-        lib().orc_batch_mask(_p(self.states), self.n, _p(m), _p(nl))
+        lib().orc_batch_mask(_p(self.states), self.n, self._cfgp(), _p(m), _p(nl))
         return m, nl
 
     def sample(self, mask, num_legal):
@@ -194,7 +196,7 @@ class OracleEngine:
     def resample(self, per, seed, game_id_base=0):
         """New engine holding per resamples of each game (game ids base + i*per + j)."""
         out = OracleEngine(self.n * per, seed, self.cfg.k_battleless, self.cfg.max_moves,
-                           bool(self.cfg.auto_reset), reset=False)
+                           bool(self.cfg.auto_reset), reset=False, two_square=bool(self.cfg.two_square))
         lib().orc_batch_resample(_p(self.states), self.n, per, seed, game_id_base, _p(out.states))
         return out
 
@@ -212,13 +214,19 @@ class OracleEngine:
                             _p(r["reason"]), _p(r["ep_len"]))
         return r
 
-    def legal_list(self, game, player):
+    def legal_list(self, game, player, two_square=None):
+        ts = self.cfg.two_square if two_square is None else int(bool(two_square))
         legal = np.zeros(10000, dtype=np.uint8)
-        n = lib().orc_legal_list(self._state_ptr(game), player, _p(legal))
+        n = lib().orc_legal_list(self._state_ptr(game), player, ts, _p(legal))
         return n, legal
 
-    def has_legal_move(self, game, player):
-        return bool(lib().orc_has_legal_move(self._state_ptr(game), player))
+    def has_legal_move(self, game, player, two_square=None):
+        ts = self.cfg.two_square if two_square is None else int(bool(two_square))
+        return bool(lib().orc_has_legal_move(self._state_ptr(game), player, ts))
+
+    def two_square_applies(self, game):
+        """App. B.1 ComputeTwoSquareRuleApplies for one game."""
+        return bool(lib().orc_two_square_applies(self._state_ptr(game), self._cfgp()))
 
     def terminal_check(self, game):
         lib().orc_terminal_check(self._state_ptr(game), self._cfgp())

@@ -16,6 +16,7 @@
  *   App. B  (GPU simulator: reset behaviour, API table, auto-reset)
  *   App. C  (Information state: C.1 board channels 0-455, C.2 recent moves)
  *   App. D.1 (game-rule hyper-parameters: k-move rule, max game length)
+ *   App. B.2 (two-square rule state machine)
  *
  * Pinning status of each part (how the tests tie it to something other
  * than itself):
@@ -31,6 +32,9 @@
  *   encoding layout ........... pinned by invariants and hand-built positions
  *   resampler ................. pinned by invariants and by agreement of its
  *                               empirical frequencies with the probability channels
+ *   two-square rule ........... pinned by hand-built move sequences written
+ *                               from the rule's statement (App. A), including
+ *                               Scout spans; the Scout case is a reading
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -67,7 +71,7 @@ typedef struct {
     int32_t k_battleless;   /* k of the k-move rule (App. D.1: 100 in training) */
     int32_t max_moves;      /* maximum game length (App. D.1: 4000) */
     int32_t auto_reset;     /* reset terminated games to a fresh setup (App. B) */
-    int32_t pad;
+    int32_t two_square;     /* enforce the two-square rule (App. A competitive play) */
 } orc_cfg;
 
 typedef struct {
@@ -99,6 +103,12 @@ typedef struct {
     int outcome;
     int reason;
     uint32_t redraws;
+    /* two-square rule state of each player (App. B.2): the piece that player
+     * moved last and the squares it occupied, oldest first, ending on its
+     * current square (ts_n = 0: none; at most 4, i.e. three moves) */
+    int ts_piece[2];
+    int ts_n[2];
+    int ts_pos[2][4];
 } orc_state;
 
 /* ------------------------------------------------------------------ */
@@ -221,7 +231,60 @@ static uint32_t stream_next(word_stream* s) {
 
 /* ------------------------------------------------------------------ */
 /* Legal moves (App. A "Piece details").  legal[100*from+to] = 1.         */
-static int legal_actions(const orc_state* st, int player, unsigned char* legal) {
+/* ------------------------------------------------------------------ */
+/* Two-square rule (App. A: a piece may not cross the same square boundary
+ * on more than three consecutive turns of its owner; App. B.2: tracked as
+ * the last four squares of each player's last-moved piece).  A move from u
+ * to v along a row or column crosses the unit boundaries between
+ * consecutive squares of the segment; boundary k of a line lies between
+ * coordinates k and k+1 of that line. */
+typedef struct { int axis, line, lo, hi; } span;   /* boundaries lo..hi-1 */
+
+static span move_span(int u, int v) {
+    span sp;
+    int ru = u / 10, cu = u % 10, rv = v / 10, cv = v % 10;
+    if (ru == rv) { sp.axis = 0; sp.line = ru; sp.lo = cu < cv ? cu : cv; sp.hi = cu < cv ? cv : cu; }
+    else          { sp.axis = 1; sp.line = cu; sp.lo = ru < rv ? ru : rv; sp.hi = ru < rv ? rv : ru; }
+    return sp;
+}
+
+/* Would moving the player's piece from `from` to `to` cross, for the fourth
+ * consecutive own turn, a boundary its last three moves all crossed? */
+static int two_square_forbids(const orc_state* st, int player, int from, int to) {
+    if (st->ts_n[player] < 4) return 0;
+    const int* pos = st->ts_pos[player];
+    if (pos[3] != from || st->board[from] != st->ts_piece[player]) return 0;
+    span m[4] = {move_span(pos[0], pos[1]), move_span(pos[1], pos[2]), move_span(pos[2], pos[3]),
+                 move_span(from, to)};
+    int lo = m[0].lo, hi = m[0].hi;
+    for (int i = 1; i < 4; i++) {
+        if (m[i].axis != m[0].axis || m[i].line != m[0].line) return 0;
+        if (m[i].lo > lo) lo = m[i].lo;
+        if (m[i].hi < hi) hi = m[i].hi;
+    }
+    return lo < hi;
+}
+
+/* After the player's piece X moved from `from` to `to`: extend its record
+ * when it is the same piece continuing from where it stopped, else start a
+ * new one; forget it when the piece did not end on `to` (it died). */
+static void two_square_update(orc_state* st, int player, int X, int from, int to) {
+    if (st->board[to] != X) { st->ts_n[player] = 0; return; }
+    int n = st->ts_n[player];
+    int* pos = st->ts_pos[player];
+    if (n > 0 && st->ts_piece[player] == X && pos[n - 1] == from) {
+        if (n == 4) { pos[0] = pos[1]; pos[1] = pos[2]; pos[2] = pos[3]; n = 3; }
+        pos[n++] = to;
+    } else {
+        st->ts_piece[player] = X;
+        pos[0] = from;
+        pos[1] = to;
+        n = 2;
+    }
+    st->ts_n[player] = n;
+}
+
+static int legal_actions(const orc_state* st, int player, int two_square, unsigned char* legal) {
     static const int DR[4] = {-1, 1, 0, 0};
     static const int DC[4] = {0, 0, -1, 1};
     int n = 0;
@@ -240,27 +303,22 @@ static int legal_actions(const orc_state* st, int player, unsigned char* legal) 
                 int y = rr * 10 + cc;
                 if (is_lake(y)) break;
                 int o = st->board[y];
-                if (o == EMPTY) {
-                    if (legal) legal[100 * x + y] = 1;
-                    n++;
-                    continue;
-                }
-                if (owner_of(o) != player) {
+                if (o >= 0 && owner_of(o) == player) break;
+                if (!(two_square && two_square_forbids(st, player, x, y))) {
                     if (legal) legal[100 * x + y] = 1;
                     n++;
                 }
-                break;
+                if (o != EMPTY) break;
             }
         }
     }
     return n;
 }
 
-/* A player has a legal move iff one of its movable pieces has an adjacent
- * square that is empty or holds an enemy piece (a Scout's longer moves
- * always pass through such an adjacent empty square). */
-static int has_legal_move(const orc_state* st, int player) {
-    return legal_actions(st, player, NULL) > 0;
+/* A player has a legal move iff its legal list is not empty (with the
+ * two-square rule on, the list already leaves out the forbidden moves). */
+static int has_legal_move(const orc_state* st, int player, int two_square) {
+    return legal_actions(st, player, two_square, NULL) > 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -275,9 +333,9 @@ static void terminal_check(orc_state* st, const orc_cfg* cfg, int flag_captured_
         st->reason = REASON_FLAG;
         return;
     }
-    if (!has_legal_move(st, q)) {
+    if (!has_legal_move(st, q, cfg->two_square)) {
         st->done = 1;
-        if (!has_legal_move(st, 1 - q)) {
+        if (!has_legal_move(st, 1 - q, cfg->two_square)) {
             st->outcome = 0;
             st->reason = REASON_FORCED_DRAW;
         } else {
@@ -378,7 +436,7 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
     int from = action / 100, to = action % 100;
     int p = st->ply & 1, q = 1 - p;
     unsigned char legal[10000];
-    legal_actions(st, p, legal);
+    legal_actions(st, p, cfg->two_square, legal);
     if (!legal[action]) return 0;
 
     int X = st->board[from];
@@ -502,6 +560,9 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
             }
         }
     }
+
+    /* the two-square record of the mover's side */
+    two_square_update(st, p, X, from, to);
 
     /* 7-8. move history and counters */
     int slot = st->ply & (RING - 1);
@@ -699,6 +760,12 @@ static void to_record(const orc_state* st, uint8_t* rec) {
     rec[18] = (uint8_t)(int8_t)st->outcome;
     rec[19] = (uint8_t)st->reason;
     put_u32(rec, 20, st->redraws);
+    for (int p = 0; p < 2; p++) {
+        uint8_t* t = rec + 24 + 8 * p;
+        t[0] = (uint8_t)(st->ts_n[p] ? st->ts_piece[p] : 0);
+        t[1] = (uint8_t)st->ts_n[p];
+        for (int i = 0; i < st->ts_n[p]; i++) t[2 + i] = (uint8_t)st->ts_pos[p][i];
+    }
     for (int s = 0; s < NSQ; s++) rec[64 + s] = (uint8_t)(int8_t)st->board[s];
     for (int m = 0; m < RING; m++) {
         rec[164 + 2 * m] = (uint8_t)st->ring_from[m];
@@ -733,6 +800,12 @@ static void from_record(orc_state* st, const uint8_t* rec) {
     st->outcome = (int8_t)rec[18];
     st->reason = rec[19];
     st->redraws = get_u32(rec, 20);
+    for (int p = 0; p < 2; p++) {
+        const uint8_t* t = rec + 24 + 8 * p;
+        st->ts_piece[p] = t[0];
+        st->ts_n[p] = t[1];
+        for (int i = 0; i < 4; i++) st->ts_pos[p][i] = i < t[1] ? t[2 + i] : 0;
+    }
     for (int s = 0; s < NSQ; s++) st->board[s] = (int8_t)rec[64 + s];
     for (int m = 0; m < RING; m++) {
         st->ring_from[m] = rec[164 + 2 * m];
@@ -825,20 +898,20 @@ void orc_batch_reset(orc_state* s, int n, const orc_cfg* cfg, const uint32_t* ga
     }
 }
 
-static int mask_one(const orc_state* st, uint64_t* mask) {
+static int mask_one(const orc_state* st, const orc_cfg* cfg, uint64_t* mask) {
     unsigned char legal[10000];
     memset(mask, 0, MASK_WORDS * sizeof(uint64_t));
     if (st->done) return 0;
-    int n = legal_actions(st, st->ply & 1, legal);
+    int n = legal_actions(st, st->ply & 1, cfg->two_square, legal);
     for (int a = 0; a < 10000; a++)
         if (legal[a]) mask[a >> 6] |= (uint64_t)1 << (a & 63);
     return n;
 }
 
-void orc_batch_mask(const orc_state* s, int n, uint64_t* mask, int16_t* num_legal) {
+void orc_batch_mask(const orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int16_t* num_legal) {
 #pragma omp parallel for schedule(dynamic, 8)
     for (int i = 0; i < n; i++) {
-        int c = mask_one(&s[i], mask + (size_t)i * MASK_WORDS);
+        int c = mask_one(&s[i], cfg, mask + (size_t)i * MASK_WORDS);
         if (num_legal) num_legal[i] = (int16_t)c;
     }
 }
@@ -972,7 +1045,7 @@ void orc_batch_ply(orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int1
 #pragma omp parallel for schedule(dynamic, 4)
     for (int i = 0; i < n; i++) {
         uint64_t m[MASK_WORDS];
-        int c = mask_one(&s[i], m);
+        int c = mask_one(&s[i], cfg, m);
         int a = sample_one(&s[i], cfg->seed, m, c);
         if (mask) memcpy(mask + (size_t)i * MASK_WORDS, m, sizeof(m));
         if (num_legal) num_legal[i] = (int16_t)c;
@@ -1000,11 +1073,21 @@ int orc_num_threads(void) { return 1; }
 #endif
 
 /* Single-game helpers for tests. */
-int orc_legal_list(const orc_state* st, int player, unsigned char* legal10000) {
-    return legal_actions(st, player, legal10000);
+int orc_legal_list(const orc_state* st, int player, int two_square, unsigned char* legal10000) {
+    return legal_actions(st, player, two_square, legal10000);
 }
 
-int orc_has_legal_move(const orc_state* st, int player) { return has_legal_move(st, player); }
+int orc_has_legal_move(const orc_state* st, int player, int two_square) {
+    return has_legal_move(st, player, two_square);
+}
+
+/* App. B.1 ComputeTwoSquareRuleApplies: the rule is on and removes at least
+ * one move the acting player could otherwise make. */
+int orc_two_square_applies(const orc_state* st, const orc_cfg* cfg) {
+    if (!cfg->two_square || st->done) return 0;
+    int p = st->ply & 1;
+    return legal_actions(st, p, 0, NULL) != legal_actions(st, p, 1, NULL);
+}
 
 void orc_terminal_check(orc_state* st, const orc_cfg* cfg) { terminal_check(st, cfg, -1); }
 

@@ -7,6 +7,8 @@ engine's arithmetic (no move generation, battles, encoding or RNG).
 Record layout (little-endian):
   0 u32 game_id | 4 u32 episode | 8 i32 ply | 12 i32 battleless
   16 u8 ring_count | 17 u8 done | 18 i8 outcome | 19 u8 reason | 20 u32 redraws
+  24 + 8*p: two-square state of player p: u8 piece id | u8 n (0..4) | u8 squares[4]
+  (the squares the piece occupied, oldest first, the last being its square)
   64..163 i8 board[100] (piece id, -1 empty, -2 lake)
   164..227 u8 ring[32][2] (from, to); the move made at ply t sits in slot t mod 32
   256 + 16*id: u32 w0, w1, w2, w3 per piece id (0..39 red, 40..79 blue)
@@ -41,14 +43,16 @@ def sq(row, col):
 
 
 def make_record(pieces, ply=0, battleless=0, game_id=0, episode=0, moves=(), done=0,
-                outcome=0, reason=0, dead_cause=6, dead_square=None):
+                outcome=0, reason=0, dead_cause=6, dead_square=None, two_square=(None, None)):
     """pieces: list of dicts with keys sq, owner, type (name or index) and optional
     revealed, moved, id, threat, evade, adj, prot, prot_against, been_by,
     been_against.  Piece ids are taken from the owner's unused ids whose default
     type matches, unless `id` is given.  Unplaced ids become dead pieces (revealed,
     death square = their start square unless dead_square is given).
     moves: list of (from, to), oldest first; stored as the last len(moves) plies
-    before `ply`."""
+    before `ply`.
+    two_square: per player None or a list of squares (oldest first) occupied by
+    the piece that now stands on the last of them."""
     rec = np.zeros(REC_BYTES, dtype=np.uint8)
     board = np.full(100, -1, dtype=np.int8)
     for s in LAKES:
@@ -107,6 +111,12 @@ def make_record(pieces, ply=0, battleless=0, game_id=0, episode=0, moves=(), don
     rec[18] = np.uint8(np.int8(outcome))
     rec[19] = reason
     rec[64:164] = board.view(np.uint8)
+    for p, squares in enumerate(two_square):
+        if squares:
+            assert 2 <= len(squares) <= 4
+            rec[24 + 8 * p] = board[squares[-1]]
+            rec[25 + 8 * p] = len(squares)
+            rec[26 + 8 * p:26 + 8 * p + len(squares)] = squares
     for i, (f, t_) in enumerate(moves):
         plyidx = ply - len(moves) + i
         slot = plyidx % 32

@@ -20,8 +20,8 @@ MUTANTS = [
      "if (a == SPY && d == MARSHAL) return BATTLE_ATTACKER;\n    if (a == MARSHAL && d == SPY) return BATTLE_DEFENDER;",
      "battle_table"),
     ("scouts jump over pieces",
-     "        if (legal) legal[100 * x + y] = 1;\n                    n++;\n                }\n                break;",
-     "        if (legal) legal[100 * x + y] = 1;\n                    n++;\n                }\n                continue;",
+     "                if (o != EMPTY) break;\n",
+     "                if (o != EMPTY) continue;\n",
      "brute_force"),
     ("lakes are passable",
      "                if (is_lake(y)) break;\n                int o = st->board[y];",
@@ -59,6 +59,10 @@ MUTANTS = [
      "if (st->battleless >= cfg->k_battleless) {",
      "if (st->battleless > cfg->k_battleless) {",
      "terminal"),
+    ("two-square spans that only touch count as shared",
+     "    return lo < hi;\n}",
+     "    return lo <= hi;\n}",
+     "two_square"),
     ("setup shuffle skips the last swap",
      "for (int i = 39; i >= 1; i--) {\n        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));",
      "for (int i = 39; i >= 2; i--) {\n        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));",

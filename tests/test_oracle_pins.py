@@ -658,3 +658,102 @@ def test_resample_frequencies_match_probability_channels():
             p = num / den if den else 0.0
             f = (types[:, col] == t).mean()
             assert abs(f - p) < 5 * math.sqrt(max(p * (1 - p), 1e-9) / per) + 1e-9, (pid, t, f, p)
+
+
+# ---------------------------------------------------------------- two-square rule
+# App. A: a piece may not cross the same square boundary on more than three
+# consecutive turns of its owner.  The oracle tracks each player's last-moved
+# piece and the squares it occupied (App. B.2).
+def _play(e, actions):
+    for a in actions:
+        r = e.step(np.array([a], dtype=np.int16))
+        assert r["first_bad"] == -1, a
+    return r
+
+
+def _moves_of(e, frm):
+    n, legal = e.legal_list(0, e.export()[0][8] & 1)
+    return {int(a) % 100 for a in np.flatnonzero(legal) if int(a) // 100 == frm}
+
+
+def _corridor_position():
+    # red Sergeant on (3,0); blue Scout on (9,9) moving elsewhere
+    return make_record([dict(sq=sq(3, 0), owner=0, type="Sergeant"),
+                        dict(sq=sq(0, 9), owner=0, type="Flag"),
+                        dict(sq=sq(9, 9), owner=1, type="Scout"),
+                        dict(sq=sq(9, 0), owner=1, type="Flag")])
+
+
+def test_two_square_fourth_crossing_is_forbidden():
+    A, B = sq(3, 0), sq(4, 0)
+    b1, b2 = sq(9, 9), sq(9, 8)
+    seq = [100 * A + B, 100 * b1 + b2, 100 * B + A, 100 * b2 + b1, 100 * A + B, 100 * b1 + b2]
+    on = engine_from([_corridor_position()], two_square=True)
+    _play(on, seq[:4])
+    assert B in _moves_of(on, A)             # the third crossing is still allowed
+    _play(on, seq[4:])
+    assert _moves_of(on, B) == {sq(5, 0), sq(4, 1)}   # back to A would be the fourth
+    off = engine_from([_corridor_position()], two_square=False)
+    _play(off, seq)
+    assert _moves_of(off, B) == {A, sq(5, 0), sq(4, 1)}
+    # the record keeps the state; an import continues with it
+    rec = on.export()[0]
+    assert list(rec[24:30]) == [rec[64 + B], 4, A, B, A, B]
+    again = engine_from([rec], two_square=True)
+    assert _moves_of(again, B) == {sq(5, 0), sq(4, 1)}
+    # the rule is reported, and only with the flag on
+    assert on.two_square_applies(0) and not off.two_square_applies(0)
+
+
+def test_two_square_resets_when_another_piece_moves():
+    A, B = sq(3, 0), sq(4, 0)
+    rec = make_record([dict(sq=A, owner=0, type="Sergeant"), dict(sq=sq(0, 5), owner=0, type="Miner"),
+                       dict(sq=sq(0, 9), owner=0, type="Flag"), dict(sq=sq(9, 9), owner=1, type="Scout"),
+                       dict(sq=sq(9, 0), owner=1, type="Flag")])
+    e = engine_from([rec], two_square=True)
+    blue = [100 * (99 - k) + 98 - k for k in range(4)]   # the blue Scout walks west along row 9
+    _play(e, [100 * A + B, blue[0], 100 * B + A, blue[1], 100 * sq(0, 5) + sq(0, 4), blue[2],
+              100 * A + B, blue[3]])
+    assert A in _moves_of(e, B)
+    assert not e.two_square_applies(0)
+
+
+def test_two_square_scout_spans():
+    # a Scout on column 0 (no lakes): 30 -> 60 -> 40 -> 70 crosses row
+    # boundaries {3,4,5}, {4,5}, {4,5,6}; boundaries 4 and 5 were crossed on
+    # all three turns, so from 70 any move crossing 4 or 5 is forbidden
+    rec = make_record([dict(sq=sq(3, 0), owner=0, type="Scout"), dict(sq=sq(0, 9), owner=0, type="Flag"),
+                       dict(sq=sq(9, 9), owner=1, type="Scout"), dict(sq=sq(9, 5), owner=1, type="Flag")])
+    e = engine_from([rec], two_square=True)
+    b1, b2 = sq(9, 9), sq(9, 8)
+    _play(e, [100 * 30 + 60, 100 * b1 + b2, 100 * 60 + 40, 100 * b2 + b1, 100 * 40 + 70, 100 * b1 + b2])
+    got = _moves_of(e, 70)
+    row7 = {sq(7, c) for c in range(1, 10)}
+    assert got == {60, 80, 90} | row7
+    e_off = engine_from([rec], two_square=False)
+    _play(e_off, [100 * 30 + 60, 100 * b1 + b2, 100 * 60 + 40, 100 * b2 + b1, 100 * 40 + 70, 100 * b1 + b2])
+    assert _moves_of(e_off, 70) == {0, 10, 20, 30, 40, 50, 60, 80, 90} | row7
+    # a turn along another line breaks the run: 30 -> 60 -> 40 -> 41 restricts nothing
+    e2 = engine_from([rec], two_square=True)
+    _play(e2, [100 * 30 + 60, 100 * b1 + b2, 100 * 60 + 40, 100 * b2 + b1, 100 * 40 + 41, 100 * b1 + b2])
+    n_on, _ = e2.legal_list(0, 0, two_square=True)
+    n_off, _ = e2.legal_list(0, 0, two_square=False)
+    assert n_on == n_off
+
+
+def test_two_square_can_leave_no_legal_move():
+    # the red Sergeant shuttles in a dead end walled by its own Bombs: after
+    # three crossings it has no move left and red loses (forced win for blue)
+    walls = [dict(sq=s, owner=0, type="Bomb") for s in (sq(0, 1), sq(1, 1), sq(2, 0))]
+    pieces = [dict(sq=sq(0, 0), owner=0, type="Sergeant"), dict(sq=sq(0, 9), owner=0, type="Flag")] + walls + [
+        dict(sq=sq(9, 9), owner=1, type="Scout"), dict(sq=sq(9, 0), owner=1, type="Flag")]
+    rec = make_record(pieces)
+    A, B = sq(0, 0), sq(1, 0)
+    b1, b2 = sq(9, 9), sq(9, 8)
+    seq = [100 * A + B, 100 * b1 + b2, 100 * B + A, 100 * b2 + b1, 100 * A + B, 100 * b1 + b2]
+    on = engine_from([rec], two_square=True)
+    r = _play(on, seq)
+    assert r["done"][0] == 1 and r["outcome"][0] == -1 and r["reason"][0] == 2
+    off = engine_from([rec], two_square=False)
+    r = _play(off, seq)
+    assert r["done"][0] == 0
