@@ -215,6 +215,36 @@ def rollout_buffer_bench(E, torch, n=GAMES, H=64, warm=256):
     return out
 
 
+def two_square_bench(E, torch, n=GAMES, warm=256, timed=128):
+    """The fused ply with the two-square rule on (App. A competitive play):
+    same workload as the headline run, rule enforced in masks and terminal
+    tests; also the share of games the rule restricts at the end."""
+    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True, two_square=True)
+    obs = eng.obs
+
+    def plies():
+        E.stratego_run_plies(eng.ctx, GRAPH_PLIES, obs=obs, use_graph=True)
+    for _ in range(warm // GRAPH_PLIES):
+        plies()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(timed // GRAPH_PLIES):
+        plies()
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / timed
+    applies = torch.empty(n, dtype=torch.uint8, device="cuda")
+    E.stratego_history_info(eng.ctx, eng.window()[1], None, n, two_square_applies=applies)
+    share = float(applies.float().mean())
+    assert eng.error() == (0, -1)
+    eng.close()
+    out = dict(ms_per_ply=ms, game_steps_per_s=n / (ms / 1e3), restricted_share=share,
+               workload=f"{n} games, fused ply with observations, two-square rule on")
+    print(f"[bench] two-square rule: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +366,8 @@ def main():
     serving = None if args.no_serving else serving_bench(E, torch)
     torch.cuda.empty_cache()
     rollout_buffer = None if args.no_history else rollout_buffer_bench(E, torch, n)
+    torch.cuda.empty_cache()
+    two_square = None if args.no_history else two_square_bench(E, torch, n)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -372,6 +404,7 @@ def main():
         "plain_engine": plain,
         "serving": serving,
         "rollout_buffer": rollout_buffer,
+        "two_square_rule": two_square,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }

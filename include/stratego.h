@@ -72,6 +72,8 @@ typedef struct {
   int32_t lds_layout;     /* observation staging in LDS: 1 = bit planes; 2..6 = byte images in
                              1, 2, 4, 8, 16 channel segments; 0 = default (1) */
   int32_t history_len;    /* rollout buffer: time steps kept (App. B.1), 0..2^20; 0 = none */
+  int32_t two_square_rule; /* 1: a piece may not cross the same square boundary on more than
+                              three consecutive turns of its owner (App. A, App. B.2) */
 } stratego_config;
 
 /* Create a context with N games, all reset to fresh setups (episode 0).
@@ -271,6 +273,9 @@ int stratego_history_encode_obs(stratego_ctx* ctx, int64_t t, const int32_t* gam
  *   has_legal_movement  uint8: the acting player has a legal move in a live
  *                              game (GetHasLegalMovement)
  *   flag_captured       uint8: the action at t captured a Flag (GetFlagCaptured)
+ *   two_square_applies  uint8: the two-square rule is on and removes at least
+ *                              one move the acting player could otherwise make
+ *                              (ComputeTwoSquareRuleApplies)
  *   is_unknown          uint8 [count][100]: 1 on squares holding an opponent
  *                              piece whose type the acting player has not seen
  *                              (ComputeIsUnknownPiece), acting player's frame
@@ -289,6 +294,7 @@ typedef struct {
   uint8_t* flag_captured;
   uint8_t* is_unknown;
   uint8_t* piece_onehot;
+  uint8_t* two_square_applies;
 } stratego_history_outputs;
 int stratego_history_info(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
                           const stratego_history_outputs* out);

@@ -33,6 +33,7 @@ constexpr int kOffDone = 17;
 constexpr int kOffOutcome = 18;
 constexpr int kOffReason = 19;
 constexpr int kOffRedraws = 20;
+constexpr int kOffTwoSquare = 24;   // per player p at +8p: u8 piece, u8 n, u8 squares[4]
 constexpr int kOffBoard = 64;
 constexpr int kOffRing = 164;
 constexpr int kOffPieces = 256;
@@ -93,6 +94,7 @@ struct Rules {
   int32_t k_battleless;
   int32_t max_moves;
   int32_t auto_reset;
+  int32_t two_square;   // enforce the two-square rule
 };
 
 // ---------------------------------------------------------------- wave helpers
@@ -279,15 +281,95 @@ __device__ __forceinline__ void destinations(const uint8_t* R, int x, int p, uin
   }
 }
 
+// ---------------------------------------------------------------- two-square rule
+// App. A (competitive play): a piece may not cross the same square boundary
+// on more than three consecutive turns of its owner.  App. B.2: the record
+// keeps, per player, the last-moved piece and up to four squares it occupied
+// (oldest first, the last being its square).  A move along a row or column
+// crosses the unit boundaries between consecutive squares of its segment.
+struct Span { int axis, line, lo, hi; };   // boundaries lo..hi-1 of the line
+
+__device__ __forceinline__ Span span_of(int u, int v) {
+  const int ru = u / 10, cu = u - 10 * ru, rv = v / 10, cv = v - 10 * rv;
+  Span sp;
+  if (ru == rv) { sp.axis = 0; sp.line = ru; sp.lo = cu < cv ? cu : cv; sp.hi = cu < cv ? cv : cu; }
+  else { sp.axis = 1; sp.line = cu; sp.lo = ru < rv ? ru : rv; sp.hi = ru < rv ? rv : ru; }
+  return sp;
+}
+
+// The tracked piece of player p is restricted when it made the last three
+// recorded moves of its side and they all crossed a common boundary: then
+// returns true with its square x, the axis (0 row, 1 column) of their line,
+// and the interval [L, H) of boundaries all three crossed.
+__device__ __forceinline__ bool two_square_window(const uint8_t* R, int p, int& x, int& axis, int& L, int& H) {
+  const uint8_t* t = R + kOffTwoSquare + 8 * p;
+  x = t[5];
+  if (t[1] != 4 || board_at(R, x) != (int)t[0]) return false;
+  const Span a = span_of(t[2], t[3]), b = span_of(t[3], t[4]), c = span_of(t[4], t[5]);
+  if (a.axis != b.axis || a.axis != c.axis || a.line != b.line || a.line != c.line) return false;
+  axis = a.axis;
+  L = max(a.lo, max(b.lo, c.lo));
+  H = min(a.hi, min(b.hi, c.hi));
+  return L < H;
+}
+
+// Does a move from x to y along the window's line cross a boundary in [L, H)?
+__device__ __forceinline__ bool window_hit(int x, int y, int axis, int L, int H) {
+  const int rx = x / 10, cx = x - 10 * rx, ry = y / 10, cy = y - 10 * ry;
+  if (axis == 0 ? ry != rx : cy != cx) return false;
+  const int u = axis == 0 ? cx : rx, v = axis == 0 ? cy : ry;
+  return max(L, min(u, v)) < min(H, max(u, v));
+}
+
+// Does the rule forbid player p's move from -> to?
+__device__ __forceinline__ bool two_square_forbids(const uint8_t* R, int p, int from, int to) {
+  int x, axis, L, H;
+  return two_square_window(R, p, x, axis, L, H) && x == from && window_hit(x, to, axis, L, H);
+}
+
+// Removes from the destination set (lo, hi) of the restricted piece's square
+// the moves the rule forbids (only squares on the window's line can be hit).
+__device__ __forceinline__ void two_square_clear(int x, int axis, int L, int H, uint64_t& lo, uint64_t& hi) {
+  const int r = x / 10, c = x - 10 * r;
+  for (int k = 0; k < 10; ++k) {
+    const int y = axis == 0 ? 10 * r + k : 10 * k + c;
+    if (y != x && window_hit(x, y, axis, L, H)) {
+      if (y < 64) lo &= ~(1ull << y);
+      else hi &= ~(1ull << (y - 64));
+    }
+  }
+}
+
+// After player p's piece X moved from -> to: extend its record when it is the
+// same piece continuing from where it stopped, else start a new one; forget
+// it when the piece did not end on `to`.  Single lane.
+__device__ __forceinline__ void two_square_update(uint8_t* R, int p, int X, int from, int to) {
+  uint8_t* t = R + kOffTwoSquare + 8 * p;
+  const int n = t[1];
+  if (board_at(R, to) != X) {
+    for (int i = 0; i < 6; ++i) t[i] = 0;
+  } else if (n > 0 && (int)t[0] == X && (int)t[1 + n] == from) {
+    if (n == 4) { t[2] = t[3]; t[3] = t[4]; t[4] = t[5]; t[5] = (uint8_t)to; }
+    else { t[2 + n] = (uint8_t)to; t[1] = (uint8_t)(n + 1); }
+  } else {
+    t[0] = (uint8_t)X; t[1] = 2; t[2] = (uint8_t)from; t[3] = (uint8_t)to; t[4] = 0; t[5] = 0;
+  }
+}
+
 // True when player p owns a movable piece with an adjacent empty or enemy
-// square, i.e. p has at least one legal move.
-__device__ __forceinline__ bool has_move(const uint8_t* R, int p) {
+// square, i.e. p has at least one legal move (with the two-square rule, the
+// tracked piece counts only through its allowed moves).
+__device__ __forceinline__ bool has_move(const uint8_t* R, int p, bool two_square) {
   const int lane = lane_id();
+  // the restricted piece (at most one) counts only through its allowed moves
+  int rx = -1, axis = 0, L = 0, H = 0;
+  if (!(two_square && two_square_window(R, p, rx, axis, L, H))) rx = -1;
   bool any = false;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     int x = lane + 64 * h;
     if (x >= kSquares) break;
+    if (x == rx) continue;
     int id = board_at(R, x);
     if (id < 0 || owner(id) != p || !movable_type(p_type(piece_words(R, id)[0]))) continue;
 #pragma unroll
@@ -298,12 +380,24 @@ __device__ __forceinline__ bool has_move(const uint8_t* R, int p) {
       if (o == kEmpty || (o >= 0 && owner(o) != p)) any = true;
     }
   }
-  return ballot(any) != 0;
+  if (ballot(any) != 0) return true;
+  if (rx < 0) return false;
+  // a longer Scout move crosses the boundary next to rx that the one-square
+  // move in its direction crosses, so the one-square moves decide
+  bool some = false;
+  if (lane < 4) {
+    const int y = neighbour(rx, lane);
+    if (y >= 0) {
+      const int o = board_at(R, y);
+      some = (o == kEmpty || (o >= 0 && owner(o) != p)) && !window_hit(rx, y, axis, L, H);
+    }
+  }
+  return ballot(some) != 0;
 }
 
 // Direct test of one action against the movement rule (used to validate
 // caller-supplied actions).
-__device__ __forceinline__ bool action_is_legal(const uint8_t* R, int p, int action) {
+__device__ __forceinline__ bool action_is_legal(const uint8_t* R, int p, int action, bool two_square) {
   if (action < 0 || action >= 10000) return false;
   int from = action / 100, to = action - 100 * from;
   if (from == to) return false;
@@ -320,13 +414,13 @@ __device__ __forceinline__ bool action_is_legal(const uint8_t* R, int p, int act
   int stp = rf == rt ? (ct > cf ? 1 : -1) : (rt > rf ? 10 : -10);
   for (int y = from + stp; y != to; y += stp)
     if (board_at(R, y) != kEmpty) return false;
-  return true;
+  return !(two_square && two_square_forbids(R, p, from, to));
 }
 
 // Mask words of the acting player: lane l returns words l, 64+l, 128+l (the
 // last only for l < 29).  ts is the LDS array of 100 destination sets
 // (2 x u64 each).  Returns the number of legal actions (wave-uniform).
-__device__ __forceinline__ int legal_mask_words(const uint8_t* R, uint64_t* ts, uint64_t w[3]) {
+__device__ __forceinline__ int legal_mask_words(const uint8_t* R, uint64_t* ts, uint64_t w[3], bool two_square) {
   const int lane = lane_id();
   const int p = hdr_u32(R, kOffPly) & 1;
   const bool done = R[kOffDone] != 0;
@@ -345,6 +439,18 @@ __device__ __forceinline__ int legal_mask_words(const uint8_t* R, uint64_t* ts, 
   }
   if (lane == 0) { ts[200] = 0; ts[201] = 0; }   // sentinel set after square 99
   wave_sync();
+  int rx, axis, L, H;
+  if (two_square && !done && two_square_window(R, p, rx, axis, L, H)) {
+    if (lane == 0) {
+      uint64_t lo = ts[2 * rx], hi = ts[2 * rx + 1];
+      const int before = __popcll(lo) + __popcll(hi);
+      two_square_clear(rx, axis, L, H, lo, hi);
+      ts[2 * rx] = lo;
+      ts[2 * rx + 1] = hi;
+      cnt -= before - (__popcll(lo) + __popcll(hi));
+    }
+    wave_sync();
+  }
 #pragma unroll
   for (int g = 0; g < 3; ++g) {
     int word = lane + 64 * g;
@@ -411,15 +517,15 @@ __device__ __forceinline__ int sample_from_words(const uint64_t w[3], int n, uin
 // App. A: capture of the flag wins; a player to move without legal moves loses,
 // a draw when neither side can move; App. D.1: k-move rule, maximum length.
 // Priority: flag > no moves > k-move > max moves.  Writes done/outcome/reason.
-__device__ __forceinline__ void terminal_check(uint8_t* R, const Rules& rules, int flag_winner) {
+__device__ __forceinline__ void terminal_check(uint8_t* R, Rules rules, int flag_winner) {
   const int ply = (int)hdr_u32(R, kOffPly);
   const int q = ply & 1;
   int done = 0, outcome = 0, reason = kReasonNone;
   if (flag_winner >= 0) {
     done = 1; outcome = flag_winner == 0 ? 1 : -1; reason = kReasonFlag;
-  } else if (!has_move(R, q)) {
+  } else if (!has_move(R, q, rules.two_square)) {
     done = 1;
-    if (!has_move(R, 1 - q)) { outcome = 0; reason = kReasonForcedDraw; }
+    if (!has_move(R, 1 - q, rules.two_square)) { outcome = 0; reason = kReasonForcedDraw; }
     else { outcome = (1 - q) == 0 ? 1 : -1; reason = kReasonForcedWin; }
   } else if ((int)hdr_u32(R, kOffBattleless) >= rules.k_battleless) {
     done = 1; reason = kReasonKMove;
@@ -450,7 +556,7 @@ __device__ __forceinline__ int initial_count(int t) {
 // Fresh uniformly random setup of both players for (game id, episode): a
 // Durstenfeld shuffle of the multiset per player, red id i on square i, blue
 // id 40+i on square 99-i.
-__device__ void fresh_setup(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_t game_id,
+__device__ __forceinline__ void fresh_setup(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_t game_id,
                             uint32_t episode, uint32_t redraws) {
   const int lane = lane_id();
   uint4* r4 = reinterpret_cast<uint4*>(R);
@@ -494,7 +600,7 @@ __device__ void fresh_setup(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_
   wave_sync();
 }
 
-__device__ void reset_game(uint8_t* R, uint8_t* scratch, const Rules& rules, uint32_t game_id,
+__device__ __forceinline__ void reset_game(uint8_t* R, uint8_t* scratch, Rules rules, uint32_t game_id,
                            uint32_t episode, uint32_t redraws) {
   fresh_setup(R, scratch, rules.seed, game_id, episode, redraws);
   terminal_check(R, rules, -1);
@@ -519,7 +625,7 @@ __device__ void reset_game(uint8_t* R, uint8_t* scratch, const Rules& rules, uin
 // non-battle reply to a threat in which the mover newly becomes adjacent to a
 // square next to the threatener).  Then pushes the move into the ring,
 // advances the counters and runs the terminal check.
-__device__ void apply_action(uint8_t* R, const Rules& rules, int action) {
+__device__ __forceinline__ void apply_action(uint8_t* R, Rules rules, int action) {
   const int lane = lane_id();
   const int from = action / 100, to = action - 100 * (action / 100);
   const int ply = (int)hdr_u32(R, kOffPly);
@@ -645,6 +751,8 @@ __device__ void apply_action(uint8_t* R, const Rules& rules, int action) {
         }
       }
     }
+    // the two-square record of the mover's side
+    two_square_update(R, p, X, from, to);
     // 7-8. ring and counters
     const int slot = ply & 31;
     R[kOffRing + 2 * slot] = (uint8_t)from;
@@ -664,7 +772,10 @@ struct StepOut {
 };
 
 // One ApplyActions step of one game (App. B).  Returns the per-game outputs.
-__device__ StepOut step_game(uint8_t* R, uint8_t* scratch, const Rules& rules, int action) {
+// validate: check the action against the rules first (caller-supplied
+// actions); actions drawn from the legal mask skip the check.
+template <bool validate>
+__device__ __forceinline__ StepOut step_game(uint8_t* R, uint8_t* scratch, Rules rules, int action) {
   StepOut o{0, 0, 0, 0, false};
   if (R[kOffDone]) {
     o.done = 1;
@@ -677,8 +788,7 @@ __device__ StepOut step_game(uint8_t* R, uint8_t* scratch, const Rules& rules, i
     return o;
   }
   if (action == -1) return o;
-  const int p = hdr_u32(R, kOffPly) & 1;
-  if (!action_is_legal(R, p, action)) {
+  if (validate && !action_is_legal(R, hdr_u32(R, kOffPly) & 1, action, rules.two_square)) {
     o.illegal = true;
     return o;
   }
@@ -759,7 +869,7 @@ __device__ __forceinline__ int frame_of(int o, int s) { return o == 0 ? s : 99 -
 // zeroed image segments (App. C.1 channel table, App. C.2 move planes).  Every
 // attribute of a piece appears twice: in its owner's "own" channel and in the
 // opponent's "opponent" channel, each in that observer's frame.
-__device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, const Rules& rules,
+__device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, Rules rules,
                                 const SegWriter& W) {
   const int lane = lane_id();
   const int ply = (int)hdr_u32(R, kOffPly);
@@ -903,7 +1013,7 @@ __device__ __forceinline__ void stream_out(u32x4* im, u32x4* dst, int chunks) {
 // bytes) with the byte-image layout: per segment of channels, scatter both
 // observers' non-zero bytes into the zero LDS images, then stream both
 // segments to HBM.
-__device__ void encode_game_bytes(const uint8_t* R, uint8_t* slab, const Rules& rules, int segments,
+__device__ void encode_game_bytes(const uint8_t* R, uint8_t* slab, Rules rules, int segments,
                                   uint8_t* obs) {
   const int segc = seg_channels_for(segments), segb = seg_bytes_for(segments);
   uint8_t* img = slab + kSlabImage;
@@ -1079,7 +1189,7 @@ __device__ __forceinline__ void stream_bitplanes(const uint8_t* slab, int o, uin
   }
 }
 
-__device__ void encode_game_bits(const uint8_t* R, uint8_t* slab, const Rules& rules, uint8_t* obs) {
+__device__ void encode_game_bits(const uint8_t* R, uint8_t* slab, Rules rules, uint8_t* obs) {
   clear_lds(slab + kSlabImage, image_bytes_for(kLayoutBits));
   build_bitplanes(R, slab);
   const uint32_t c41 = 0x01010101u * quant255(hdr_u32(R, kOffPly), (uint32_t)rules.max_moves);
@@ -1092,7 +1202,7 @@ __device__ void encode_game_bits(const uint8_t* R, uint8_t* slab, const Rules& r
 // Encode both observers with the given LDS layout.  The byte-image layouts
 // expect a zero image on entry and leave it zero; the bit-plane layout clears
 // its planes itself.
-__device__ void encode_game(const uint8_t* R, uint8_t* slab, const Rules& rules, int layout,
+__device__ void encode_game(const uint8_t* R, uint8_t* slab, Rules rules, int layout,
                             uint8_t* obs) {
   if (layout == kLayoutBits) encode_game_bits(R, slab, rules, obs);
   else encode_game_bytes(R, slab, rules, segments_of(layout), obs);
@@ -1213,6 +1323,15 @@ __device__ bool record_ok(const uint8_t* R) {
       (int)hdr_u32(R, kOffPly) < 0 || (int)hdr_u32(R, kOffPly) > 32767 ||
       (int)hdr_u32(R, kOffBattleless) < 0)
     bad = true;
+  // two-square records: 0 or 2-4 squares on the board, of a piece id of that
+  // player, unused bytes zero
+  if (lane < 2) {
+    const uint8_t* t = R + kOffTwoSquare + 8 * lane;
+    if (t[1] > 4 || t[1] == 1) bad = true;
+    if (t[1] > 0 ? (t[0] >= kPieces || owner(t[0]) != lane) : t[0] != 0) bad = true;
+    for (int i = 0; i < 4; ++i)
+      if (i < t[1] ? t[2 + i] >= kSquares : t[2 + i] != 0) bad = true;
+  }
   return ballot(bad) == 0;
 }
 

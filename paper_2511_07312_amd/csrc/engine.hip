@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       int action = -1;
       if (MODE & kDoMask) {
         uint64_t w[3];
-        const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
+        const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules.two_square);
         fetch_next();
         if (a.mask) {
           uint64_t* m = a.mask + (size_t)oi * kMaskWords;
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       }
       if (MODE & kDoStep) {
         if (a.hist) store_record(a.hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
-        StepOut o = step_game(R, slab + kSlabScratch, a.rules, action);
+        StepOut o = step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, a.rules, action);
         if (lane == 0) {
           const size_t row = (size_t)a.out_base + oi;
           if (a.done) a.done[row] = (int8_t)o.done;
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
   load_record(R, src);
   if (Q == kQMask) {
     uint64_t w[3];
-    const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
+    const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, h.rules.two_square);
     if (h.mask) {
       uint64_t* m = h.mask + (size_t)i * kMaskWords;
 #pragma unroll
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
     const stratego_history_outputs& o = h.out;
     const int ply = (int)hdr_u32(R, kOffPly), p = ply & 1;
     const bool done = R[kOffDone] != 0;
-    const bool movable = has_move(R, p) && !done;   // wave-wide
+    const bool movable = has_move(R, p, h.rules.two_square) && !done;   // wave-wide
     // per-square views in the acting player's frame
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -447,6 +447,18 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
       if (o.terminated_since) o.terminated_since[i] = since;
       if (o.has_legal_movement) o.has_legal_movement[i] = (uint8_t)movable;
       if (o.flag_captured) o.flag_captured[i] = (uint8_t)(ended && sreason == kReasonFlag);
+      if (o.two_square_applies) {   // the rule removes a move the acting player could otherwise make
+        bool applies = false;
+        int x, axis, L, H;
+        if (h.rules.two_square && !done && two_square_window(R, p, x, axis, L, H)) {
+          uint64_t lo, hi;
+          destinations(R, x, p, lo, hi);
+          const uint64_t lo0 = lo, hi0 = hi;
+          two_square_clear(x, axis, L, H, lo, hi);
+          applies = lo != lo0 || hi != hi0;
+        }
+        o.two_square_applies[i] = (uint8_t)applies;
+      }
     }
   }
 }
@@ -494,6 +506,7 @@ inline Rules rules_of(const stratego_ctx* c) {
   r.k_battleless = c->cfg.k_battleless;
   r.max_moves = c->cfg.max_moves;
   r.auto_reset = c->cfg.auto_reset;
+  r.two_square = c->cfg.two_square_rule;
   return r;
 }
 
@@ -647,7 +660,8 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
   if (!cfg || !out) return STRATEGO_E_INVAL;
   *out = nullptr;
   if (cfg->num_games <= 0 || cfg->k_battleless <= 0 || cfg->max_moves <= 0 ||
-      cfg->max_moves > 32767 || (cfg->auto_reset != 0 && cfg->auto_reset != 1))
+      cfg->max_moves > 32767 || (cfg->auto_reset != 0 && cfg->auto_reset != 1) ||
+      (cfg->two_square_rule != 0 && cfg->two_square_rule != 1))
     return STRATEGO_E_INVAL;
   int G = cfg->games_per_wg ? cfg->games_per_wg : 1;
   int S = cfg->lds_layout ? cfg->lds_layout : kLayoutBits;
