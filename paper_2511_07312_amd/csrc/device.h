@@ -55,15 +55,15 @@ constexpr int kSlabImage = 1792;    // obs image segment (also holds the to-squa
 //     staged at once (6.1 KB each) and expanded to bytes while streaming out;
 //   2..6: byte images of both observers in 1, 2, 4, 8, 16 channel segments.
 constexpr int kLayoutBits = 1;
-__host__ __device__ constexpr bool valid_layout(int L) { return L >= 1 && L <= 6; }
-__host__ __device__ constexpr int segments_of(int L) { return L <= 1 ? 1 : 1 << (L - 2); }
+__host__ __device__ __forceinline__ constexpr bool valid_layout(int L) { return L >= 1 && L <= 6; }
+__host__ __device__ __forceinline__ constexpr int segments_of(int L) { return L <= 1 ? 1 : 1 << (L - 2); }
 
 // Channels per image segment (multiples of 4, so segments stay 16-byte aligned).
-__host__ __device__ constexpr int seg_channels_for(int segments) {
+__host__ __device__ __forceinline__ constexpr int seg_channels_for(int segments) {
   return segments == 1 ? 488 : segments == 2 ? 244 : segments == 4 ? 124 : segments == 8 ? 64 : 32;
 }
 // Bytes of one observer's image segment; both observers' segments are staged.
-__host__ __device__ constexpr int seg_bytes_for(int segments) { return 100 * seg_channels_for(segments); }
+__host__ __device__ __forceinline__ constexpr int seg_bytes_for(int segments) { return 100 * seg_channels_for(segments); }
 
 // bit-plane layout: plane bit 100*c + f of observer o <=> byte (c, f) is 1 (or
 // 255 / a table value in the special regions); move sources in a side plane
@@ -78,11 +78,11 @@ constexpr int kBitsCat1 = kBitsCat0 + 112;
 constexpr int kBitsTab = kBitsCat1 + 112;                 // uint64 [2][24]
 constexpr int kBitsSlabBytes = kBitsTab + 2 * 24 * 8;
 
-__host__ __device__ constexpr int slab_bytes_for(int L) {
+__host__ __device__ __forceinline__ constexpr int slab_bytes_for(int L) {
   return L == kLayoutBits ? kBitsSlabBytes : kSlabImage + 2 * seg_bytes_for(segments_of(L));
 }
 // LDS bytes that must be zero when a game's encoding starts
-__host__ __device__ constexpr int image_bytes_for(int L) {
+__host__ __device__ __forceinline__ constexpr int image_bytes_for(int L) {
   return L == kLayoutBits ? kBitsCat0 - kSlabImage : 2 * seg_bytes_for(segments_of(L));
 }
 
@@ -361,9 +361,10 @@ __device__ __forceinline__ void two_square_update(uint8_t* R, int p, int X, int 
 // tracked piece counts only through its allowed moves).
 __device__ __forceinline__ bool has_move(const uint8_t* R, int p, bool two_square) {
   const int lane = lane_id();
-  // the restricted piece (at most one) counts only through its allowed moves
-  int rx = -1, axis = 0, L = 0, H = 0;
-  if (!(two_square && two_square_window(R, p, rx, axis, L, H))) rx = -1;
+  // the piece the two-square rule may restrict: it counts only through its
+  // allowed moves (tested below); -1 when none
+  const uint8_t* t = R + kOffTwoSquare + 8 * p;
+  const int rx = __builtin_amdgcn_readfirstlane(two_square && t[1] == 4 ? (int)t[5] : -1);
   bool any = false;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -384,12 +385,15 @@ __device__ __forceinline__ bool has_move(const uint8_t* R, int p, bool two_squar
   if (rx < 0) return false;
   // a longer Scout move crosses the boundary next to rx that the one-square
   // move in its direction crosses, so the one-square moves decide
+  int x, axis, L, H;
+  const bool window = two_square_window(R, p, x, axis, L, H);
   bool some = false;
   if (lane < 4) {
+    const int id = board_at(R, rx);
     const int y = neighbour(rx, lane);
-    if (y >= 0) {
+    if (id >= 0 && owner(id) == p && movable_type(p_type(piece_words(R, id)[0])) && y >= 0) {
       const int o = board_at(R, y);
-      some = (o == kEmpty || (o >= 0 && owner(o) != p)) && !window_hit(rx, y, axis, L, H);
+      some = (o == kEmpty || (o >= 0 && owner(o) != p)) && !(window && window_hit(rx, y, axis, L, H));
     }
   }
   return ballot(some) != 0;
@@ -550,7 +554,8 @@ __device__ __forceinline__ int multiset_type(int i) {
 }
 
 __device__ __forceinline__ int initial_count(int t) {
-  return t == 0 ? 1 : t == 1 ? 8 : t == 2 ? 5 : t <= 5 ? 4 : t == 6 ? 3 : t == 7 ? 2 : t <= 10 ? 1 : 6;
+  // 4 bits per type, Spy first: 1 8 5 4 4 4 3 2 1 1 1 6 (branch-free lookup)
+  return (int)((0x611123444581ull >> (4 * t)) & 15u);
 }
 
 // Fresh uniformly random setup of both players for (game id, episode): a
@@ -817,7 +822,7 @@ __device__ __forceinline__ uint32_t quant255(uint32_t num, uint32_t den) {
   return den == 0 ? 0u : (510u * num + den) / (2u * den);
 }
 
-__device__ void compute_probq(const uint8_t* R, uint8_t* slab) {
+__device__ __forceinline__ void compute_probq(const uint8_t* R, uint8_t* slab) {
   const int lane = lane_id();
   int* cnt = reinterpret_cast<int*>(slab + kSlabCounts);   // known[2][12], H[2], M[2]
   if (lane < 28) cnt[lane] = 0;
@@ -869,7 +874,7 @@ __device__ __forceinline__ int frame_of(int o, int s) { return o == 0 ? s : 99 -
 // zeroed image segments (App. C.1 channel table, App. C.2 move planes).  Every
 // attribute of a piece appears twice: in its owner's "own" channel and in the
 // opponent's "opponent" channel, each in that observer's frame.
-__device__ void scatter_segment(const uint8_t* R, const uint8_t* slab, Rules rules,
+__device__ __forceinline__ void scatter_segment(const uint8_t* R, const uint8_t* slab, Rules rules,
                                 const SegWriter& W) {
   const int lane = lane_id();
   const int ply = (int)hdr_u32(R, kOffPly);
@@ -1013,7 +1018,7 @@ __device__ __forceinline__ void stream_out(u32x4* im, u32x4* dst, int chunks) {
 // bytes) with the byte-image layout: per segment of channels, scatter both
 // observers' non-zero bytes into the zero LDS images, then stream both
 // segments to HBM.
-__device__ void encode_game_bytes(const uint8_t* R, uint8_t* slab, Rules rules, int segments,
+__device__ __forceinline__ void encode_game_bytes(const uint8_t* R, uint8_t* slab, Rules rules, int segments,
                                   uint8_t* obs) {
   const int segc = seg_channels_for(segments), segb = seg_bytes_for(segments);
   uint8_t* img = slab + kSlabImage;
@@ -1047,7 +1052,7 @@ __device__ __forceinline__ uint32_t expand4(uint32_t n) { return (n * 0x00204081
 // values from per-square categories (1/2 opponent hidden moved/unmoved, 3/4
 // own hidden moved/unmoved) and a per-channel table; the planes carry only the
 // 255 of revealed types there.
-__device__ void build_bitplanes(const uint8_t* R, uint8_t* slab) {
+__device__ __forceinline__ void build_bitplanes(const uint8_t* R, uint8_t* slab) {
   const int lane = lane_id();
   const int ply = (int)hdr_u32(R, kOffPly);
 #pragma unroll 1
@@ -1189,7 +1194,7 @@ __device__ __forceinline__ void stream_bitplanes(const uint8_t* slab, int o, uin
   }
 }
 
-__device__ void encode_game_bits(const uint8_t* R, uint8_t* slab, Rules rules, uint8_t* obs) {
+__device__ __forceinline__ void encode_game_bits(const uint8_t* R, uint8_t* slab, Rules rules, uint8_t* obs) {
   clear_lds(slab + kSlabImage, image_bytes_for(kLayoutBits));
   build_bitplanes(R, slab);
   const uint32_t c41 = 0x01010101u * quant255(hdr_u32(R, kOffPly), (uint32_t)rules.max_moves);
@@ -1202,7 +1207,7 @@ __device__ void encode_game_bits(const uint8_t* R, uint8_t* slab, Rules rules, u
 // Encode both observers with the given LDS layout.  The byte-image layouts
 // expect a zero image on entry and leave it zero; the bit-plane layout clears
 // its planes itself.
-__device__ void encode_game(const uint8_t* R, uint8_t* slab, Rules rules, int layout,
+__device__ __forceinline__ void encode_game(const uint8_t* R, uint8_t* slab, Rules rules, int layout,
                             uint8_t* obs) {
   if (layout == kLayoutBits) encode_game_bits(R, slab, rules, obs);
   else encode_game_bytes(R, slab, rules, segments_of(layout), obs);
@@ -1215,7 +1220,7 @@ __device__ void encode_game(const uint8_t* R, uint8_t* slab, Rules rules, int la
 // hidden pieces (partial Fisher-Yates in ascending id order, Flag first), then
 // the movable multiset shuffled over the remaining hidden pieces in ascending
 // id order.  Runs on lane 0.
-__device__ void resample_game(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_t new_id) {
+__device__ __forceinline__ void resample_game(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_t new_id) {
   const int lane = lane_id();
   if (lane == 0) {
     const int z = 1 - (int)(hdr_u32(R, kOffPly) & 1);
@@ -1276,7 +1281,7 @@ __device__ void resample_game(uint8_t* R, uint8_t* scratch, uint64_t seed, uint3
 // movable pieces have moved, death squares/causes and ring squares in range,
 // counters in range.  Everything the kernels index by record contents is
 // covered, so a rejected record can never drive an out-of-range access.
-__device__ bool record_ok(const uint8_t* R) {
+__device__ __forceinline__ bool record_ok(const uint8_t* R) {
   const int lane = lane_id();
   bool bad = false;
   int my_type[2] = {-1, -1};

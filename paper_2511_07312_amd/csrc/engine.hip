@@ -70,7 +70,7 @@ __device__ __forceinline__ uint64_t pack_step(int action, const StepOut& o) {
 // and parked in the spare buffer before the observation stream starts, so no
 // global load is waited on right after a burst of stores (on gfx950 one
 // counter tracks both, and waiting for a load would also drain the stores).
-__host__ __device__ constexpr int wave_lds_bytes(int layout) { return slab_bytes_for(layout) + kRecordBytes; }
+__host__ __device__ __forceinline__ constexpr int wave_lds_bytes(int layout) { return slab_bytes_for(layout) + kRecordBytes; }
 
 template <int MODE, bool BITS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ply(PlyArgs a) {
@@ -358,7 +358,7 @@ struct HistArgs {
   Rules rules;
 };
 
-__host__ __device__ constexpr int hist_lds_bytes(int q) {
+__host__ __device__ __forceinline__ constexpr int hist_lds_bytes(int q) {
   return q == kQObs ? slab_bytes_for(kLayoutBits)
        : q == kQMask ? kSlabImage + kDestSetBytes
        : q == kQInfo ? kRecordBytes : 16;
