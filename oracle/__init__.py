@@ -18,5 +18,8 @@ from .oracle import (  # noqa: F401
     REC_BYTES,
     MASK_WORDS,
     NCHAN,
+    MAX_LEGAL,
+    SAMPLER_UNIFORM,
+    SAMPLER_MAGNET,
 )
 from .history import OracleRolloutBuffer, WindowError  # noqa: F401,E402

@@ -10,6 +10,8 @@ _SRC = os.path.join(_HERE, "stratego_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 REC_BYTES = 1536
+MAX_LEGAL = 256
+SAMPLER_UNIFORM, SAMPLER_MAGNET = 0, 1
 MASK_WORDS = 157
 NCHAN = 488
 OBS_BYTES = 2 * NCHAN * 100
@@ -20,7 +22,7 @@ def build(force=True):
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-shared", "-fPIC",
-                               _SRC, "-o", tmp])
+                               _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -28,7 +30,7 @@ def build(force=True):
 class _Cfg(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("k_battleless", ctypes.c_int32),
                 ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
-                ("two_square", ctypes.c_int32)]
+                ("two_square", ctypes.c_int32), ("sampler", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -62,6 +64,10 @@ def lib():
         L.orc_has_legal_move.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.orc_has_legal_move.restype = ctypes.c_int
         L.orc_two_square_applies.argtypes = [P, P]
+        L.orc_batch_legal_list.argtypes = [P, ctypes.c_int, P, P, P]
+        L.orc_batch_magnet.argtypes = [P, ctypes.c_int, P, P]
+        L.orc_batch_mmd.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double, P]
+        L.orc_batch_sample_policy.argtypes = [P, ctypes.c_int, P, P, P]
         L.orc_two_square_applies.restype = ctypes.c_int
         L.orc_terminal_check.argtypes = [P, P]
         L.orc_battle.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -121,12 +127,13 @@ class OracleEngine:
     """N independent games advanced by the C oracle."""
 
     def __init__(self, n, seed, k_battleless=100, max_moves=1000, auto_reset=False,
-                 game_ids=None, reset=True, two_square=False):
+                 game_ids=None, reset=True, two_square=False, sampler=SAMPLER_UNIFORM):
         L = lib()
         self.n = int(n)
         self.sb = int(L.orc_state_bytes())
         self.states = np.zeros(self.n * self.sb, dtype=np.uint8)
-        self.cfg = _Cfg(seed, k_battleless, max_moves, 1 if auto_reset else 0, 1 if two_square else 0)
+        self.cfg = _Cfg(seed, k_battleless, max_moves, 1 if auto_reset else 0, 1 if two_square else 0,
+                        int(sampler), 0)
         if reset:
             self.reset(game_ids)
 
@@ -196,7 +203,8 @@ class OracleEngine:
     def resample(self, per, seed, game_id_base=0):
         """New engine holding per resamples of each game (game ids base + i*per + j)."""
         out = OracleEngine(self.n * per, seed, self.cfg.k_battleless, self.cfg.max_moves,
-                           bool(self.cfg.auto_reset), reset=False, two_square=bool(self.cfg.two_square))
+                           bool(self.cfg.auto_reset), reset=False, two_square=bool(self.cfg.two_square),
+                           sampler=self.cfg.sampler)
         lib().orc_batch_resample(_p(self.states), self.n, per, seed, game_id_base, _p(out.states))
         return out
 
@@ -213,6 +221,35 @@ class OracleEngine:
                             _p(r["actions"]), _p(r["obs"]), _p(r["done"]), _p(r["outcome"]),
                             _p(r["reason"]), _p(r["ep_len"]))
         return r
+
+    # -- policies over the legal list (section 2.4, App. D.7) ---------------
+    def legal_actions_list(self):
+        """Legal actions of every game in ascending order, padded with -1."""
+        a = np.zeros((self.n, MAX_LEGAL), dtype=np.int16)
+        nl = np.zeros(self.n, dtype=np.int16)
+        lib().orc_batch_legal_list(_p(self.states), self.n, self._cfgp(), _p(a), _p(nl))
+        return a, nl
+
+    def magnet(self):
+        """The magnet policy over each game's legal list (float32)."""
+        out = np.zeros((self.n, MAX_LEGAL), dtype=np.float32)
+        lib().orc_batch_magnet(_p(self.states), self.n, self._cfgp(), _p(out))
+        return out
+
+    def mmd(self, q, logpi, alpha, beta):
+        """The search policy over each legal list, in float64."""
+        out = np.zeros((self.n, MAX_LEGAL), dtype=np.float64)
+        lib().orc_batch_mmd(_p(self.states), self.n, self._cfgp(),
+                            _p(np.ascontiguousarray(q, dtype=np.float32)),
+                            _p(np.ascontiguousarray(logpi, dtype=np.float32)), float(alpha), float(beta),
+                            _p(out))
+        return out
+
+    def sample_policy(self, probs):
+        a = np.zeros(self.n, dtype=np.int16)
+        lib().orc_batch_sample_policy(_p(self.states), self.n, self._cfgp(),
+                                      _p(np.ascontiguousarray(probs, dtype=np.float32)), _p(a))
+        return a
 
     def legal_list(self, game, player, two_square=None):
         ts = self.cfg.two_square if two_square is None else int(bool(two_square))

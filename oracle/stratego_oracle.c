@@ -40,6 +40,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <stdio.h>
+#include <math.h>
 
 /* ------------------------------------------------------------------ */
 /* Pieces (App. A, Table "pieces").  Type index follows the channel order
@@ -64,7 +65,8 @@ enum { REASON_NONE = 0, REASON_FLAG = 1, REASON_FORCED_WIN = 2,
 
 enum { BATTLE_ATTACKER = 0, BATTLE_DEFENDER = 1, BATTLE_TIE = 2 };
 
-enum { TAG_MOVE = 0, TAG_SETUP0 = 1, TAG_SETUP1 = 2, TAG_RESAMPLE = 3 };
+enum { TAG_MOVE = 0, TAG_SETUP0 = 1, TAG_SETUP1 = 2, TAG_RESAMPLE = 3, TAG_POLICY = 4 };
+enum { SAMPLER_UNIFORM = 0, SAMPLER_MAGNET = 1 };
 
 typedef struct {
     uint64_t seed;
@@ -72,6 +74,8 @@ typedef struct {
     int32_t max_moves;      /* maximum game length (App. D.1: 4000) */
     int32_t auto_reset;     /* reset terminated games to a fresh setup (App. B) */
     int32_t two_square;     /* enforce the two-square rule (App. A competitive play) */
+    int32_t sampler;        /* move sampler: 0 uniform over legal actions, 1 magnet policy */
+    int32_t pad;
 } orc_cfg;
 
 typedef struct {
@@ -919,13 +923,41 @@ void orc_batch_mask(const orc_state* s, int n, const orc_cfg* cfg, uint64_t* mas
 /* Uniform legal action (App. B "SampleRandomLegalAction"): the r-th legal
  * action in ascending id order, r = bounded(Philox(seed; game, ply,
  * episode, MOVE).x, n). */
-static int sample_one(const orc_state* st, uint64_t seed, const uint64_t* mask, int n) {
+static int mask_bit(const uint64_t* mask, int a) { return (int)((mask[a >> 6] >> (a & 63)) & 1); }
+
+/* Legal moves of the piece on square x in a mask (its actions 100x..100x+99). */
+static int moves_from(const uint64_t* mask, int x) {
+    int m = 0;
+    for (int y = 0; y < NSQ; y++) m += mask_bit(mask, 100 * x + y);
+    return m;
+}
+
+static int sample_one(const orc_state* st, const orc_cfg* cfg, const uint64_t* mask, int n) {
     if (n <= 0 || st->done) return -1;
     uint32_t w[4];
-    philox_block(seed, st->game_id, (uint32_t)st->ply, st->episode, TAG_MOVE, w);
+    philox_block(cfg->seed, st->game_id, (uint32_t)st->ply, st->episode, TAG_MOVE, w);
+    if (cfg->sampler == SAMPLER_MAGNET) {
+        /* the magnet policy (section 2.3, App. D: a movable piece uniformly at
+         * random, then one of its legal moves uniformly at random): the
+         * r1-th piece with a legal move in ascending square order, r1 =
+         * bounded(y, P), then its r2-th move in ascending destination order,
+         * r2 = bounded(z, m) */
+        int P = 0;
+        for (int x = 0; x < NSQ; x++) P += moves_from(mask, x) > 0;
+        int r1 = (int)bounded(w[1], (uint32_t)P);
+        for (int x = 0; x < NSQ; x++) {
+            int m = moves_from(mask, x);
+            if (m == 0) continue;
+            if (r1-- > 0) continue;
+            int r2 = (int)bounded(w[2], (uint32_t)m);
+            for (int y = 0; y < NSQ; y++)
+                if (mask_bit(mask, 100 * x + y) && r2-- == 0) return 100 * x + y;
+        }
+        return -1;
+    }
     int r = (int)bounded(w[0], (uint32_t)n);
     for (int a = 0; a < 10000; a++) {
-        if (mask[a >> 6] & ((uint64_t)1 << (a & 63))) {
+        if (mask_bit(mask, a)) {
             if (r == 0) return a;
             r--;
         }
@@ -937,8 +969,7 @@ void orc_batch_sample(const orc_state* s, int n, const orc_cfg* cfg, const uint6
                       const int16_t* num_legal, int16_t* actions) {
 #pragma omp parallel for schedule(dynamic, 8)
     for (int i = 0; i < n; i++)
-        actions[i] = (int16_t)sample_one(&s[i], cfg->seed, mask + (size_t)i * MASK_WORDS,
-                                         num_legal[i]);
+        actions[i] = (int16_t)sample_one(&s[i], cfg, mask + (size_t)i * MASK_WORDS, num_legal[i]);
 }
 
 /* Step one game.  Output convention: done=1 with the finished episode's
@@ -1046,7 +1077,7 @@ void orc_batch_ply(orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int1
     for (int i = 0; i < n; i++) {
         uint64_t m[MASK_WORDS];
         int c = mask_one(&s[i], cfg, m);
-        int a = sample_one(&s[i], cfg->seed, m, c);
+        int a = sample_one(&s[i], cfg, m, c);
         if (mask) memcpy(mask + (size_t)i * MASK_WORDS, m, sizeof(m));
         if (num_legal) num_legal[i] = (int16_t)c;
         if (actions) actions[i] = (int16_t)a;
@@ -1061,6 +1092,104 @@ void orc_batch_ply(orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int1
         if (outcome) outcome[i] = oc;
         if (reason) reason[i] = r;
         if (ep_len) ep_len[i] = el;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Policies over the legal list (section 2.4, App. D.7).  A game's legal list
+ * is its legal actions in ascending order, padded to MAX_LEGAL with -1.    */
+#define MAX_LEGAL 256
+
+void orc_batch_legal_list(const orc_state* s, int n, const orc_cfg* cfg, int16_t* actions,
+                          int16_t* num_legal) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++) {
+        uint64_t m[MASK_WORDS];
+        int c = mask_one(&s[i], cfg, m), k = 0;
+        int16_t* out = actions + (size_t)i * MAX_LEGAL;
+        for (int a = 0; a < 10000; a++)
+            if (mask_bit(m, a)) out[k++] = (int16_t)a;
+        for (; k < MAX_LEGAL; k++) out[k] = -1;
+        num_legal[i] = (int16_t)c;
+    }
+}
+
+/* The magnet policy rho over the legal list: 1 / (P * m), P pieces with a
+ * legal move, m the moves of the listed action's piece (one IEEE single
+ * division); 0 on padding. */
+void orc_batch_magnet(const orc_state* s, int n, const orc_cfg* cfg, float* probs) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++) {
+        uint64_t m[MASK_WORDS];
+        mask_one(&s[i], cfg, m);
+        int P = 0, k = 0;
+        for (int x = 0; x < NSQ; x++) P += moves_from(m, x) > 0;
+        float* out = probs + (size_t)i * MAX_LEGAL;
+        for (int a = 0; a < 10000; a++)
+            if (mask_bit(m, a)) out[k++] = 1.0f / (float)(P * moves_from(m, a / 100));
+        for (; k < MAX_LEGAL; k++) out[k] = 0.0f;
+    }
+}
+
+/* The search policy of App. D.7: the maximiser of <q, pi> - alpha KL(pi, rho)
+ * - beta KL(pi, pi_theta), i.e. pi proportional to
+ * [exp(q) rho^alpha pi_theta^beta]^(1/(alpha+beta)), over the legal list, in
+ * double precision.  q and logpi (log pi_theta) are given per listed action. */
+void orc_batch_mmd(const orc_state* s, int n, const orc_cfg* cfg, const float* q, const float* logpi,
+                   double alpha, double beta, double* out) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++) {
+        uint64_t m[MASK_WORDS];
+        int c = mask_one(&s[i], cfg, m);
+        int P = 0;
+        for (int x = 0; x < NSQ; x++) P += moves_from(m, x) > 0;
+        double e[MAX_LEGAL];
+        double top = -1e300, sum = 0.0;
+        int k = 0;
+        for (int a = 0; a < 10000; a++) {
+            if (!mask_bit(m, a)) continue;
+            double rho = 1.0 / ((double)P * (double)moves_from(m, a / 100));
+            size_t j = (size_t)i * MAX_LEGAL + k;
+            e[k] = ((double)q[j] + alpha * log(rho) + beta * (double)logpi[j]) / (alpha + beta);
+            if (e[k] > top) top = e[k];
+            k++;
+        }
+        for (k = 0; k < c; k++) { e[k] = exp(e[k] - top); sum += e[k]; }
+        double* o = out + (size_t)i * MAX_LEGAL;
+        for (k = 0; k < MAX_LEGAL; k++) o[k] = k < c ? e[k] / sum : 0.0;
+    }
+}
+
+/* Sample from a caller distribution over the legal list: u = the top 24
+ * bits of word x of Philox(seed; game, ply, episode, POLICY) as a fraction;
+ * the first listed action whose single-precision running sum (in list
+ * order) exceeds u times the single-precision total; the last action with a
+ * positive weight if rounding leaves none. */
+void orc_batch_sample_policy(const orc_state* s, int n, const orc_cfg* cfg, const float* probs,
+                             int16_t* actions) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < n; i++) {
+        uint64_t m[MASK_WORDS];
+        int c = mask_one(&s[i], cfg, m);
+        int list[MAX_LEGAL], k = 0;
+        for (int a = 0; a < 10000; a++)
+            if (mask_bit(m, a)) list[k++] = a;
+        const float* p = probs + (size_t)i * MAX_LEGAL;
+        int pick = -1;
+        if (c > 0 && !s[i].done) {
+            uint32_t w[4];
+            philox_block(cfg->seed, s[i].game_id, (uint32_t)s[i].ply, s[i].episode, TAG_POLICY, w);
+            float total = 0.0f;
+            for (k = 0; k < c; k++) total += p[k];
+            float t = (float)(w[0] >> 8) * (1.0f / 16777216.0f) * total;
+            float run = 0.0f;
+            for (k = 0; k < c; k++) {
+                run += p[k];
+                if (p[k] > 0.0f) pick = list[k];
+                if (run > t && p[k] > 0.0f) break;
+            }
+        }
+        actions[i] = (int16_t)pick;
     }
 }
 

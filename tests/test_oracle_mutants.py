@@ -63,6 +63,18 @@ MUTANTS = [
      "    return lo < hi;\n}",
      "    return lo <= hi;\n}",
      "two_square"),
+    ("magnet counts the destination square's moves",
+     "out[k++] = 1.0f / (float)(P * moves_from(m, a / 100));",
+     "out[k++] = 1.0f / (float)(P * moves_from(m, a % 100));",
+     "magnet"),
+    ("magnet sampler never picks the last piece",
+     "int r1 = (int)bounded(w[1], (uint32_t)P);",
+     "int r1 = (int)bounded(w[1], (uint32_t)(P > 1 ? P - 1 : 1));",
+     "magnet_sampler"),
+    ("search policy pushes away from the magnet",
+     "e[k] = ((double)q[j] + alpha * log(rho) + beta * (double)logpi[j]) / (alpha + beta);",
+     "e[k] = ((double)q[j] - alpha * log(rho) + beta * (double)logpi[j]) / (alpha + beta);",
+     "search_policy"),
     ("setup shuffle skips the last swap",
      "for (int i = 39; i >= 1; i--) {\n        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));",
      "for (int i = 39; i >= 2; i--) {\n        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));",
@@ -78,7 +90,7 @@ def test_pins_catch_planted_mistake(tmp_path, name, orig, bad, pins):
     mutant.write_text(src.replace(orig, bad))
     lib = tmp_path / "libmutant.so"
     subprocess.check_call(["gcc", "-O1", "-std=c11", "-fopenmp", "-shared", "-fPIC", str(mutant),
-                           "-o", str(lib)])
+                           "-o", str(lib), "-lm"])
     env = dict(os.environ, STRATEGO_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     kexpr = " or ".join(f"{w}" for w in pins.split(" or "))
     r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),

@@ -757,3 +757,127 @@ def test_two_square_can_leave_no_legal_move():
     off = engine_from([rec], two_square=False)
     r = _play(off, seq)
     assert r["done"][0] == 0
+
+
+# ---------------------------------------------------------------- magnet policy and search policy
+# Section 2.3 / App. D: the magnet policy rho picks a movable piece uniformly
+# at random, then one of its legal moves uniformly at random.  App. D.7: the
+# search plays pi_search = argmax <q, pi> - alpha KL(pi, rho) - beta KL(pi, pi_theta).
+def _replicate(rec, n):
+    recs = np.repeat(rec[None], n, axis=0).copy()
+    recs[:, 0:4] = np.arange(n, dtype=np.uint32).view(np.uint8).reshape(n, 4)   # game ids 0..n-1
+    return recs
+
+
+def _two_piece_position():
+    # red Sergeant boxed in to 2 moves, red Scout with a long column, blue far away
+    return make_record([dict(sq=sq(0, 0), owner=0, type="Sergeant"), dict(sq=sq(0, 1), owner=0, type="Bomb"),
+                        dict(sq=sq(2, 5), owner=0, type="Scout"), dict(sq=sq(0, 9), owner=0, type="Flag"),
+                        dict(sq=sq(9, 9), owner=1, type="Flag"), dict(sq=sq(9, 0), owner=1, type="Bomb")])
+
+
+def test_magnet_probabilities_closed_form():
+    e = engine_from([make_record([dict(sq=sq(2, 4), owner=0, type="Scout")]), _two_piece_position()])
+    acts, nl = e.legal_actions_list()
+    rho = e.magnet()
+    assert nl[0] == 18 and np.all(rho[0, :18] == np.float32(1.0 / 18)) and np.all(rho[0, 18:] == 0)
+    k = int(nl[1])
+    frm = acts[1, :k] // 100
+    sergeant = frm == sq(0, 0)
+    assert sergeant.sum() == 1                     # only (1,0): (0,1) holds its own Bomb
+    scout_moves = int((frm == sq(2, 5)).sum())
+    assert np.all(rho[1, :k][sergeant] == np.float32(1 / 2))
+    assert np.all(rho[1, :k][~sergeant] == np.float32(1.0) / np.float32(2 * scout_moves))
+    assert abs(float(rho[1].sum()) - 1.0) < 1e-6
+    assert np.all(acts[1, k:] == -1) and list(acts[1, :k]) == sorted(acts[1, :k])
+
+
+def test_magnet_sampler_is_uniform_over_pieces_then_moves():
+    from scipy.stats import chisquare
+    n = 6000
+    rec = _two_piece_position()
+    e = O.OracleEngine.from_records(_replicate(rec, n), seed=13, sampler=O.SAMPLER_MAGNET)
+    m, nl = e.mask()
+    a = e.sample(m, nl)
+    frm = a // 100
+    assert set(np.unique(frm)) == {sq(0, 0), sq(2, 5)}
+    n_sgt = int((frm == sq(0, 0)).sum())
+    assert chisquare([n_sgt, n - n_sgt]).pvalue > 1e-3          # pieces equally likely
+    scout = a[frm == sq(2, 5)]
+    _, counts = np.unique(scout, return_counts=True)
+    assert chisquare(counts).pvalue > 1e-3                     # moves of the Scout equally likely
+    u = O.OracleEngine.from_records(_replicate(rec, n), seed=13)   # the uniform sampler for contrast
+    ua = u.sample(*u.mask())
+    assert (ua // 100 == sq(0, 0)).mean() < 0.2
+
+
+def _objective(pi, q, rho, pth, alpha, beta):
+    kl = lambda p, r: float(np.sum(np.where(p > 0, p * np.log(np.where(p > 0, p, 1) / r), 0.0)))
+    return float(np.dot(q, pi)) - alpha * kl(pi, rho) - beta * kl(pi, pth)
+
+
+def test_search_policy_maximises_the_regularised_objective():
+    rng = np.random.default_rng(5)
+    recs = [_two_piece_position(), make_record([dict(sq=sq(2, 4), owner=0, type="Scout"),
+                                                dict(sq=sq(7, 7), owner=1, type="Flag")])]
+    e = engine_from(recs)
+    acts, nl = e.legal_actions_list()
+    rho = e.magnet().astype(np.float64)
+    for alpha, beta in ((0.002, 0.02), (0.5, 0.3), (1.0, 0.0)):
+        q = np.zeros((2, 256), np.float32)
+        lp = np.zeros((2, 256), np.float32)
+        pth = []
+        for g in range(2):
+            k = int(nl[g])
+            q[g, :k] = rng.uniform(-1, 1, k)
+            logits = rng.normal(0, 1, k)
+            lp[g, :k] = logits - np.log(np.exp(logits).sum())
+            pth.append(np.exp(lp[g, :k].astype(np.float64)))
+        pi = e.mmd(q, lp, alpha, beta)
+        for g in range(2):
+            k = int(nl[g])
+            p = pi[g, :k]
+            assert abs(p.sum() - 1) < 1e-12 and np.all(pi[g, k:] == 0)
+            best = _objective(p, q[g, :k].astype(np.float64), rho[g, :k], pth[g], alpha, beta)
+            for _ in range(300):   # no other point of the simplex does better
+                r = rng.dirichlet(np.ones(k) * rng.uniform(0.2, 5))
+                mix = rng.uniform(0, 1)
+                cand = mix * r + (1 - mix) * p
+                assert _objective(cand, q[g, :k].astype(np.float64), rho[g, :k], pth[g], alpha, beta) <= best + 1e-12
+
+
+def test_search_policy_special_cases():
+    e = engine_from([_two_piece_position()])
+    acts, nl = e.legal_actions_list()
+    k = int(nl[0])
+    rho = e.magnet()
+    q = np.zeros((1, 256), np.float32)
+    lp = np.zeros((1, 256), np.float32)
+    lp[0, :k] = np.log(rho[0, :k].astype(np.float64))
+    # q = 0 and pi_theta = rho: the regularisers agree, so pi = rho
+    assert np.allclose(e.mmd(q, lp, 0.002, 0.02)[0, :k], rho[0, :k], rtol=1e-6)
+    # a large advantage on one action with weak regularisation takes almost all mass
+    q[0, 3] = 1.0
+    assert e.mmd(q, lp, 0.002, 0.02)[0, 3] > 0.999
+
+
+def test_policy_sampler_follows_the_given_distribution():
+    from scipy.stats import chisquare
+    n = 8000
+    rec = _two_piece_position()
+    e = O.OracleEngine.from_records(_replicate(rec, n), seed=3)
+    acts, nl = e.legal_actions_list()
+    k = int(nl[0])
+    probs = np.zeros((n, 256), np.float32)
+    w = np.arange(1, k + 1, dtype=np.float64)
+    w[2] = 0.0                                   # a zero-weight action is never played
+    probs[:, :k] = (w / w.sum()).astype(np.float32)
+    a = e.sample_policy(probs)
+    idx = np.searchsorted(acts[0, :k], a)
+    assert np.all(acts[0, idx] == a) and not np.any(idx == 2)
+    counts = np.bincount(idx, minlength=k).astype(np.float64)
+    keep = w > 0
+    assert chisquare(counts[keep], f_exp=n * w[keep] / w.sum()).pvalue > 1e-3
+    one = np.zeros((n, 256), np.float32)
+    one[:, 5] = 1.0
+    assert np.all(e.sample_policy(one) == acts[0, 5])
