@@ -58,6 +58,9 @@ extern "C" {
 #define STRATEGO_RECORD_BYTES 1536
 #define STRATEGO_OBS_BYTES_PER_GAME 97600
 #define STRATEGO_HISTORY_BYTES_PER_GAME_STEP 1544  /* rollout buffer: record + step outcome */
+#define STRATEGO_MAX_LEGAL 256   /* legal-list capacity; a position has at most 244 legal moves */
+#define STRATEGO_SAMPLER_UNIFORM 0
+#define STRATEGO_SAMPLER_MAGNET 1
 
 typedef struct stratego_ctx stratego_ctx;
 
@@ -74,6 +77,9 @@ typedef struct {
   int32_t history_len;    /* rollout buffer: time steps kept (App. B.1), 0..2^20; 0 = none */
   int32_t two_square_rule; /* 1: a piece may not cross the same square boundary on more than
                               three consecutive turns of its owner (App. A, App. B.2) */
+  int32_t sampler;         /* move sampler of stratego_sample_actions and the fused plies:
+                              0 uniform over legal actions; 1 magnet policy (section 2.3: a
+                              piece with a legal move uniformly, then one of its moves) */
 } stratego_config;
 
 /* Create a context with N games, all reset to fresh setups (episode 0).
@@ -304,6 +310,38 @@ int stratego_history_info(stratego_ctx* ctx, int64_t t, const int32_t* games_dev
  * those games to t (App. B.1: capturing past states for search). */
 int stratego_history_export(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
                             void* states_dev);
+
+/* Policies over legal lists (section 2.3 and App. D.7).  A game's legal list
+ * is its acting player's legal actions in ascending order, padded to
+ * STRATEGO_MAX_LEGAL entries with -1 (finished games: all -1).  Per-action
+ * arrays are float[N][256] aligned with the list; entries past num_legal are
+ * ignored on input and written as 0 on output. */
+
+/* actions_dev int16[N][256]: the legal lists; num_legal_dev int16[N] or NULL. */
+int stratego_legal_list(stratego_ctx* ctx, int16_t* actions_dev, int16_t* num_legal_dev);
+
+/* The magnet policy rho (section 2.3 / App. D: a piece with a legal move
+ * uniformly at random, then one of its legal moves uniformly at random):
+ * probs_dev float[N][256], rho = 1 / (P * m) as one IEEE single division,
+ * P = pieces with a legal move, m = legal moves of the listed action's piece. */
+int stratego_magnet_policy(stratego_ctx* ctx, float* probs_dev);
+
+/* The search policy of App. D.7: the maximiser of <q, pi> - alpha KL(pi, rho)
+ * - beta KL(pi, pi_theta), i.e. pi proportional to [exp(q) rho^alpha
+ * pi_theta^beta]^(1 / (alpha + beta)), over each legal list, in single
+ * precision.  q_dev: advantage estimates, logpi_dev: log pi_theta, both
+ * float[N][256]; alpha, beta >= 0 with alpha + beta > 0 (the paper's search
+ * uses alpha = 0.002, beta = 0.02).  probs_dev float[N][256]. */
+int stratego_search_policy(stratego_ctx* ctx, const float* q_dev, const float* logpi_dev, float alpha,
+                           float beta, float* probs_dev);
+
+/* One action per game from a distribution over its legal list (probs_dev
+ * float[N][256]): u = the top 24 bits of word x of Philox4x32-10(key = seed,
+ * counter = (game id, ply, episode, 4)) as a fraction; the first listed
+ * action whose single-precision running sum, in list order, exceeds u times
+ * the single-precision total; the last action with a positive weight if
+ * rounding leaves none; -1 for an empty list.  actions_dev int16[N]. */
+int stratego_sample_policy(stratego_ctx* ctx, const float* probs_dev, int16_t* actions_dev);
 
 /* Synchronise the stream, then report and clear the latched device error:
  * returns STRATEGO_OK, E_ILLEGAL_ACTION or E_BAD_STATE; first_bad_slot (may

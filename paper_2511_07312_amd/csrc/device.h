@@ -95,7 +95,10 @@ struct Rules {
   int32_t max_moves;
   int32_t auto_reset;
   int32_t two_square;   // enforce the two-square rule
+  int32_t sampler;      // 0: uniform over legal actions; 1: magnet policy
 };
+enum : int { kSamplerUniform = 0, kSamplerMagnet = 1 };
+constexpr int kMaxLegal = 256;   // legal-list capacity (at most 244 legal moves exist)
 
 // ---------------------------------------------------------------- wave helpers
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -515,6 +518,44 @@ __device__ __forceinline__ int sample_from_words(const uint64_t w[3], int n, uin
     base += total;
   }
   return -1;
+}
+
+// Magnet policy sample (section 2.3, App. D: a movable piece uniformly at
+// random, then one of its legal moves uniformly at random).  (lo0, hi0) is
+// the destination set of square lane, (lo1, hi1) that of square lane + 64
+// (zero beyond 99).  Same Philox block as the uniform sampler: r1 =
+// bounded(y, P) picks the r1-th square with a legal move in ascending
+// order, r2 = bounded(z, m) its r2-th destination.  -1 without moves.
+__device__ __forceinline__ int sample_magnet(uint64_t lo0, uint64_t hi0, uint64_t lo1, uint64_t hi1,
+                                             uint64_t seed, uint32_t game_id, uint32_t ply,
+                                             uint32_t episode) {
+  const int lane = lane_id();
+  const uint64_t has0 = ballot((lo0 | hi0) != 0), has1 = ballot((lo1 | hi1) != 0);
+  const int c0 = __popcll(has0), P = c0 + __popcll(has1);
+  if (P == 0) return -1;
+  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  const int r1 = (int)mulshift(u.y, (uint32_t)P);
+  const int x = r1 < c0 ? select_bit(has0, r1) : 64 + select_bit(has1, r1 - c0);
+  const int src = x & 63;
+  const uint64_t lo = x < 64 ? __shfl(lo0, src, 64) : __shfl(lo1, src, 64);
+  const uint64_t hi = x < 64 ? __shfl(hi0, src, 64) : __shfl(hi1, src, 64);
+  const int nlo = __popcll(lo), m = nlo + __popcll(hi);
+  const int r2 = (int)mulshift(u.z, (uint32_t)m);
+  const int y = r2 < nlo ? select_bit(lo, r2) : 64 + select_bit(hi, r2 - nlo);
+  (void)lane;
+  return 100 * x + y;
+}
+
+// The 100-bit destination set of square x from packed mask words (global).
+__device__ __forceinline__ void square_set_from_mask(const uint64_t* mask, int x, uint64_t& lo, uint64_t& hi) {
+  lo = 0;
+  hi = 0;
+  if (x >= kSquares) return;
+  const int a0 = 100 * x, w0 = a0 >> 6, off = a0 & 63;
+  const uint64_t m0 = mask[w0], m1 = mask[w0 + 1], m2 = w0 + 2 < kMaskWords ? mask[w0 + 2] : 0ull;
+  lo = off ? (m0 >> off) | (m1 << (64 - off)) : m0;
+  hi = off ? (m1 >> off) | (m2 << (64 - off)) : m1;
+  hi &= (1ull << 36) - 1;   // 100 - 64 bits
 }
 
 // ---------------------------------------------------------------- terminal check

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <climits>
 #include <cstdint>
 #include <cstring>
@@ -172,8 +173,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         }
         if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
         if (MODE & kDoSample) {
-          action = sample_from_words(w, n, a.rules.seed, hdr_u32(R, kOffGameId),
-                                     hdr_u32(R, kOffPly), hdr_u32(R, kOffEpisode));
+          if (a.rules.sampler == kSamplerMagnet) {
+            const uint64_t* ts = reinterpret_cast<const uint64_t*>(slab + kSlabImage);
+            const bool second = lane + 64 < kSquares;
+            action = n == 0 ? -1
+                            : sample_magnet(ts[2 * lane], ts[2 * lane + 1], second ? ts[2 * lane + 128] : 0ull,
+                                            second ? ts[2 * lane + 129] : 0ull, a.rules.seed,
+                                            hdr_u32(R, kOffGameId), hdr_u32(R, kOffPly), hdr_u32(R, kOffEpisode));
+          } else {
+            action = sample_from_words(w, n, a.rules.seed, hdr_u32(R, kOffGameId),
+                                       hdr_u32(R, kOffPly), hdr_u32(R, kOffEpisode));
+          }
           if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
         }
         wave_sync();
@@ -220,7 +230,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 // Uniform legal action from a caller-supplied mask (plain engine).
 __global__ void __launch_bounds__(256) k_sample(const uint8_t* states, int32_t n, const uint64_t* mask,
-                                               const int16_t* num_legal, int16_t* actions, uint64_t seed) {
+                                               const int16_t* num_legal, int16_t* actions, uint64_t seed,
+                                               int32_t sampler) {
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int i = blockIdx.x * (blockDim.x >> 6) + wave;
   if (i >= n) return;
@@ -236,7 +247,16 @@ __global__ void __launch_bounds__(256) k_sample(const uint8_t* states, int32_t n
     w[k] = word < kMaskWords ? mask[(size_t)i * kMaskWords + word] : 0ull;
   }
   const int nl = done ? 0 : num_legal[i];
-  const int action = sample_from_words(w, nl, seed, game_id, ply, episode);
+  int action;
+  if (sampler == kSamplerMagnet) {
+    const uint64_t* m = mask + (size_t)i * kMaskWords;
+    uint64_t lo0, hi0, lo1, hi1;
+    square_set_from_mask(m, lane, lo0, hi0);
+    square_set_from_mask(m, lane + 64, lo1, hi1);
+    action = nl == 0 ? -1 : sample_magnet(lo0, hi0, lo1, hi1, seed, game_id, ply, episode);
+  } else {
+    action = sample_from_words(w, nl, seed, game_id, ply, episode);
+  }
   if (lane == 0) actions[i] = (int16_t)action;
 }
 
@@ -463,6 +483,131 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
   }
 }
 
+// ---------------------------------------------------------------- policies over legal lists
+// Section 2.3 / App. D (magnet policy) and App. D.7 (search policy).  A
+// game's legal list is its legal actions in ascending order, padded to
+// kMaxLegal with -1; per-action inputs and outputs are aligned with it.
+enum : int { kPList = 0, kPMagnet = 1, kPSearch = 2, kPSample = 3 };
+
+struct PolicyArgs {
+  const uint8_t* states;
+  int32_t n;
+  int16_t* actions;        // list (kPList) or sampled action (kPSample)
+  int16_t* num_legal;
+  float* probs;            // kPMagnet / kPSearch output
+  const float* q;          // kPSearch: advantage estimates per listed action
+  const float* logpi;      // kPSearch: log of the network policy per listed action
+  const float* in_probs;   // kPSample: distribution per listed action
+  float alpha, beta;
+  Rules rules;
+};
+
+constexpr int kPolicyList = kSlabImage + kDestSetBytes;   // int16 [kMaxLegal] in LDS
+__host__ __device__ __forceinline__ constexpr int policy_lds_bytes() { return kPolicyList + 2 * kMaxLegal; }
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+template <int Q>
+__global__ void __launch_bounds__(256) k_policy(PolicyArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int i = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (i >= a.n) return;
+  uint8_t* slab = smem + wave * policy_lds_bytes();
+  uint8_t* R = slab;
+  load_record(R, a.states + (size_t)i * kRecordBytes);
+  const uint64_t* ts = reinterpret_cast<const uint64_t*>(slab + kSlabImage);
+  uint64_t w[3];
+  const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules.two_square);
+  // the legal list, ascending: word order, then bit order
+  int16_t* list = reinterpret_cast<int16_t*>(slab + kPolicyList);
+  int base = 0;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const int word = lane + 64 * g;
+    uint64_t v = word < kMaskWords ? w[g] : 0ull;
+    const int c = __popcll(v);
+    const int incl = wave_incl_scan(c);
+    int pos = base + incl - c;
+    while (v) {
+      list[pos++] = (int16_t)(64 * word + __ffsll((unsigned long long)v) - 1);
+      v &= v - 1;
+    }
+    base += __shfl(incl, 63, 64);
+  }
+  wave_sync();
+  const size_t row = (size_t)i * kMaxLegal;
+  if (Q == kPList) {
+    for (int k = lane; k < kMaxLegal; k += 64) a.actions[row + k] = k < n ? list[k] : (int16_t)-1;
+    if (lane == 0 && a.num_legal) a.num_legal[i] = (int16_t)n;
+    return;
+  }
+  if (Q == kPSample) {
+    if (lane == 0) {
+      int pick = -1;
+      if (n > 0) {
+        const uint4 u = philox(make_uint4(hdr_u32(R, kOffGameId), hdr_u32(R, kOffPly), hdr_u32(R, kOffEpisode), 4u),
+                               a.rules.seed);
+        const float* p = a.in_probs + row;
+        float total = 0.0f;
+        for (int k = 0; k < n; ++k) total += p[k];
+        const float t = (float)(u.x >> 8) * (1.0f / 16777216.0f) * total;
+        float run = 0.0f;
+        for (int k = 0; k < n; ++k) {
+          run += p[k];
+          if (p[k] > 0.0f) pick = list[k];
+          if (run > t && p[k] > 0.0f) break;
+        }
+      }
+      a.actions[i] = (int16_t)pick;
+    }
+    return;
+  }
+  // the magnet policy: P pieces with a legal move; m moves of an action's piece
+  const bool second = lane + 64 < kSquares;
+  const int P = __popcll(ballot((ts[2 * lane] | ts[2 * lane + 1]) != 0)) +
+                __popcll(ballot(second && (ts[2 * lane + 128] | ts[2 * lane + 129]) != 0));
+  auto moves_of = [&](int x) { return __popcll(ts[2 * x]) + __popcll(ts[2 * x + 1]); };
+  if (Q == kPMagnet) {
+    for (int k = lane; k < kMaxLegal; k += 64)
+      a.probs[row + k] = k < n ? __fdiv_rn(1.0f, (float)(P * moves_of(list[k] / 100))) : 0.0f;
+    return;
+  }
+  // kPSearch: pi proportional to exp((q + alpha log rho + beta log pi_theta) / (alpha + beta))
+  float sc[kMaxLegal / 64];
+  float top = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < kMaxLegal / 64; ++j) {
+    const int k = lane + 64 * j;
+    sc[j] = -INFINITY;
+    if (k < n) {
+      const float log_rho = -logf((float)(P * moves_of(list[k] / 100)));
+      sc[j] = (a.q[row + k] + a.alpha * log_rho + a.beta * a.logpi[row + k]) / (a.alpha + a.beta);
+      top = fmaxf(top, sc[j]);
+    }
+  }
+  top = wave_max_f(top);
+  float sum = 0.0f;
+#pragma unroll
+  for (int j = 0; j < kMaxLegal / 64; ++j) {
+    sc[j] = lane + 64 * j < n ? expf(sc[j] - top) : 0.0f;
+    sum += sc[j];
+  }
+  sum = wave_sum_f(sum);
+#pragma unroll
+  for (int j = 0; j < kMaxLegal / 64; ++j) a.probs[row + lane + 64 * j] = n > 0 ? sc[j] / sum : 0.0f;
+}
+
 struct GraphEntry {
   int32_t nplies, G, S;
   const void* ptrs[9];
@@ -507,6 +652,7 @@ inline Rules rules_of(const stratego_ctx* c) {
   r.max_moves = c->cfg.max_moves;
   r.auto_reset = c->cfg.auto_reset;
   r.two_square = c->cfg.two_square_rule;
+  r.sampler = c->cfg.sampler;
   return r;
 }
 
@@ -661,7 +807,8 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
   *out = nullptr;
   if (cfg->num_games <= 0 || cfg->k_battleless <= 0 || cfg->max_moves <= 0 ||
       cfg->max_moves > 32767 || (cfg->auto_reset != 0 && cfg->auto_reset != 1) ||
-      (cfg->two_square_rule != 0 && cfg->two_square_rule != 1))
+      (cfg->two_square_rule != 0 && cfg->two_square_rule != 1) ||
+      (cfg->sampler != kSamplerUniform && cfg->sampler != kSamplerMagnet))
     return STRATEGO_E_INVAL;
   int G = cfg->games_per_wg ? cfg->games_per_wg : 1;
   int S = cfg->lds_layout ? cfg->lds_layout : kLayoutBits;
@@ -776,7 +923,7 @@ int stratego_sample_actions(stratego_ctx* c, const uint64_t* mask, const int16_t
                             int16_t* actions) {
   if (!c || !mask || !num_legal || !actions) return STRATEGO_E_INVAL;
   hipLaunchKernelGGL(k_sample, dim3(grid_for(c->cfg.num_games, 4)), dim3(256), 0, c->stream, c->states,
-                     c->cfg.num_games, mask, num_legal, actions, c->cfg.seed);
+                     c->cfg.num_games, mask, num_legal, actions, c->cfg.seed, c->cfg.sampler);
   return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
 }
 
@@ -1265,6 +1412,70 @@ int stratego_history_export(stratego_ctx* c, int64_t t, const int32_t* games, in
   if (!states) return STRATEGO_E_INVAL;
   h.records = reinterpret_cast<uint8_t*>(states);
   return launch_hist(c, kQRecord, h);
+}
+
+}  // extern "C"
+
+namespace {
+
+int launch_policy(stratego_ctx* c, int q, PolicyArgs& a) {
+  a.states = c->states;
+  a.n = c->cfg.num_games;
+  a.rules = rules_of(c);
+  const void* fn = q == kPList ? reinterpret_cast<const void*>(&k_policy<kPList>)
+                 : q == kPMagnet ? reinterpret_cast<const void*>(&k_policy<kPMagnet>)
+                 : q == kPSearch ? reinterpret_cast<const void*>(&k_policy<kPSearch>)
+                 : reinterpret_cast<const void*>(&k_policy<kPSample>);
+  void* args[] = {&a};
+  if (hipLaunchKernel(fn, dim3(grid_for(a.n, 4)), dim3(256), args, 4 * policy_lds_bytes(), c->stream) !=
+      hipSuccess)
+    return STRATEGO_E_HIP;
+  return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stratego_legal_list(stratego_ctx* c, int16_t* actions, int16_t* num_legal) {
+  if (!c || !actions) return STRATEGO_E_INVAL;
+  PolicyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.actions = actions;
+  a.num_legal = num_legal;
+  return launch_policy(c, kPList, a);
+}
+
+int stratego_magnet_policy(stratego_ctx* c, float* probs) {
+  if (!c || !probs) return STRATEGO_E_INVAL;
+  PolicyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.probs = probs;
+  return launch_policy(c, kPMagnet, a);
+}
+
+int stratego_search_policy(stratego_ctx* c, const float* q, const float* logpi, float alpha, float beta,
+                           float* probs) {
+  if (!c || !q || !logpi || !probs || !(alpha >= 0.0f) || !(beta >= 0.0f) || !(alpha + beta > 0.0f) ||
+      !std::isfinite(alpha + beta))
+    return STRATEGO_E_INVAL;
+  PolicyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.q = q;
+  a.logpi = logpi;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.probs = probs;
+  return launch_policy(c, kPSearch, a);
+}
+
+int stratego_sample_policy(stratego_ctx* c, const float* probs, int16_t* actions) {
+  if (!c || !probs || !actions) return STRATEGO_E_INVAL;
+  PolicyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in_probs = probs;
+  a.actions = actions;
+  return launch_policy(c, kPSample, a);
 }
 
 int stratego_get_error(stratego_ctx* c, int32_t* first_bad_slot) {

@@ -25,6 +25,9 @@ MASK_WORDS = 157
 RECORD_BYTES = 1536
 OBS_BYTES_PER_GAME = 97600
 HISTORY_BYTES_PER_GAME_STEP = 1544
+MAX_LEGAL = 256
+SAMPLER_UNIFORM = 0
+SAMPLER_MAGNET = 1
 
 FUNCTIONS = [
     "stratego_init", "stratego_reset", "stratego_legal_mask", "stratego_sample_actions",
@@ -33,7 +36,8 @@ FUNCTIONS = [
     "stratego_get_tiling", "stratego_set_tiling", "stratego_get_error", "stratego_current_step",
     "stratego_destroy", "stratego_strerror", "stratego_serve", "stratego_history_window",
     "stratego_history_legal_mask", "stratego_history_encode_obs", "stratego_history_info",
-    "stratego_history_export",
+    "stratego_history_export", "stratego_legal_list", "stratego_magnet_policy",
+    "stratego_search_policy", "stratego_sample_policy",
 ]
 REQ_STEP = 0
 REQ_ROLLOUT = 1
@@ -44,7 +48,8 @@ class StrategoConfig(ctypes.Structure):
                 ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("game_id_base", ctypes.c_uint32),
                 ("games_per_wg", ctypes.c_int32), ("lds_layout", ctypes.c_int32),
-                ("history_len", ctypes.c_int32), ("two_square_rule", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32), ("two_square_rule", ctypes.c_int32),
+                ("sampler", ctypes.c_int32)]
 
 
 class HistoryOutputs(ctypes.Structure):
@@ -127,6 +132,10 @@ def load_library(path=LIB_PATH):
     L.stratego_history_encode_obs.argtypes = [P, I64, P, I32, P]
     L.stratego_history_info.argtypes = [P, I64, P, I32, ctypes.POINTER(HistoryOutputs)]
     L.stratego_history_export.argtypes = [P, I64, P, I32, P]
+    L.stratego_legal_list.argtypes = [P, P, P]
+    L.stratego_magnet_policy.argtypes = [P, P]
+    L.stratego_search_policy.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, P]
+    L.stratego_sample_policy.argtypes = [P, P, P]
     L.stratego_strerror.argtypes = [ctypes.c_int]
     L.stratego_strerror.restype = ctypes.c_char_p
     for f in FUNCTIONS:
@@ -165,10 +174,11 @@ def _stream():
 
 # ------------------------------------------------------------------ C-ABI mirrors
 def stratego_init(num_games, seed, k_battleless=100, max_moves=4000, auto_reset=False,
-                  game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, two_square=False):
+                  game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, two_square=False,
+                  sampler=SAMPLER_UNIFORM):
     cfg = StrategoConfig(int(num_games), int(k_battleless), int(max_moves), int(bool(auto_reset)),
                          int(seed), int(game_id_base), int(games_per_wg), int(lds_layout),
-                         int(history_len), int(bool(two_square)))
+                         int(history_len), int(bool(two_square)), int(sampler))
     ctx = ctypes.c_void_p()
     _check(load_library().stratego_init(ctypes.byref(cfg), _stream(), ctypes.byref(ctx)),
            "stratego_init")
@@ -268,6 +278,34 @@ def stratego_history_export(ctx, t, states, games=None, count=None):
     _check(load_library().stratego_history_export(
         ctx, int(t), _ptr(games, torch.int32, m, "games"), m,
         _ptr(states, torch.uint8, m * RECORD_BYTES, "states")), "stratego_history_export")
+
+
+def stratego_legal_list(ctx, actions, num_legal=None):
+    n = _num_games(ctx)
+    _check(load_library().stratego_legal_list(
+        ctx, _ptr(actions, torch.int16, n and n * MAX_LEGAL, "actions"),
+        _ptr(num_legal, torch.int16, n, "num_legal")), "stratego_legal_list")
+
+
+def stratego_magnet_policy(ctx, probs):
+    n = _num_games(ctx)
+    _check(load_library().stratego_magnet_policy(ctx, _ptr(probs, torch.float32, n and n * MAX_LEGAL, "probs")),
+           "stratego_magnet_policy")
+
+
+def stratego_search_policy(ctx, q, logpi, alpha, beta, probs):
+    n = _num_games(ctx)
+    per = n and n * MAX_LEGAL
+    _check(load_library().stratego_search_policy(
+        ctx, _ptr(q, torch.float32, per, "q"), _ptr(logpi, torch.float32, per, "logpi"), float(alpha),
+        float(beta), _ptr(probs, torch.float32, per, "probs")), "stratego_search_policy")
+
+
+def stratego_sample_policy(ctx, probs, actions):
+    n = _num_games(ctx)
+    _check(load_library().stratego_sample_policy(
+        ctx, _ptr(probs, torch.float32, n and n * MAX_LEGAL, "probs"), _ptr(actions, torch.int16, n, "actions")),
+        "stratego_sample_policy")
 
 
 def _num_games(ctx):
@@ -376,11 +414,11 @@ class Engine:
 
     def __init__(self, num_games, seed, k_battleless=100, max_moves=1000, auto_reset=False,
                  game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, two_square=False,
-                 device="cuda"):
+                 sampler=SAMPLER_UNIFORM, device="cuda"):
         self.n = int(num_games)
         self.device = torch.device(device)
         self.ctx = stratego_init(num_games, seed, k_battleless, max_moves, auto_reset,
-                                 game_id_base, games_per_wg, lds_layout, history_len, two_square)
+                                 game_id_base, games_per_wg, lds_layout, history_len, two_square, sampler)
         n, d = self.n, self.device
         self.mask = torch.empty((n, MASK_WORDS), dtype=torch.int64, device=d)
         self.num_legal = torch.empty(n, dtype=torch.int16, device=d)
@@ -428,6 +466,28 @@ class Engine:
 
     def error(self):
         return stratego_get_error(self.ctx)
+
+    # policies over legal lists (section 2.3, App. D.7)
+    def legal_list(self):
+        a = torch.empty((self.n, MAX_LEGAL), dtype=torch.int16, device=self.device)
+        nl = torch.empty(self.n, dtype=torch.int16, device=self.device)
+        stratego_legal_list(self.ctx, a, nl)
+        return a, nl
+
+    def magnet(self):
+        p = torch.empty((self.n, MAX_LEGAL), dtype=torch.float32, device=self.device)
+        stratego_magnet_policy(self.ctx, p)
+        return p
+
+    def search_policy(self, q, logpi, alpha=0.002, beta=0.02):
+        p = torch.empty((self.n, MAX_LEGAL), dtype=torch.float32, device=self.device)
+        stratego_search_policy(self.ctx, q, logpi, alpha, beta, p)
+        return p
+
+    def sample_policy(self, probs):
+        a = torch.empty(self.n, dtype=torch.int16, device=self.device)
+        stratego_sample_policy(self.ctx, probs, a)
+        return a
 
     # rollout-buffer queries (App. B.1)
     def window(self):
