@@ -245,6 +245,54 @@ def two_square_bench(E, torch, n=GAMES, warm=256, timed=128):
     return out
 
 
+def policy_bench(E, torch, n=GAMES, warm=256, timed=128):
+    """Section 2.3 / App. D.7 at the headline size: the fused ply with the
+    magnet sampler, and the legal-list policy kernels (magnet probabilities,
+    the search policy with the paper's alpha = 0.002, beta = 0.02, and the
+    sampler over it) on 65,536 mid-game positions."""
+    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True, sampler=E.SAMPLER_MAGNET)
+    obs = eng.obs
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed_ms(fn, reps):
+        fn()
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        ev[1].synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    def plies():
+        E.stratego_run_plies(eng.ctx, GRAPH_PLIES, obs=obs, use_graph=True)
+    for _ in range(warm // GRAPH_PLIES):
+        plies()
+    ply_ms = timed_ms(plies, timed // GRAPH_PLIES) / GRAPH_PLIES
+    del obs
+    eng._obs = None
+    torch.cuda.empty_cache()
+    acts = torch.empty((n, E.MAX_LEGAL), dtype=torch.int16, device="cuda")
+    nl = torch.empty(n, dtype=torch.int16, device="cuda")
+    probs = torch.empty((n, E.MAX_LEGAL), dtype=torch.float32, device="cuda")
+    q = torch.rand((n, E.MAX_LEGAL), dtype=torch.float32, device="cuda") * 2 - 1
+    logpi = torch.full((n, E.MAX_LEGAL), -3.0, dtype=torch.float32, device="cuda")
+    picks = torch.empty(n, dtype=torch.int16, device="cuda")
+    list_ms = timed_ms(lambda: E.stratego_legal_list(eng.ctx, acts, nl), 8)
+    magnet_ms = timed_ms(lambda: E.stratego_magnet_policy(eng.ctx, probs), 8)
+    search_ms = timed_ms(lambda: E.stratego_search_policy(eng.ctx, q, logpi, 0.002, 0.02, probs), 8)
+    sample_ms = timed_ms(lambda: E.stratego_sample_policy(eng.ctx, probs, picks), 8)
+    assert eng.error() == (0, -1)
+    eng.close()
+    out = dict(magnet_ply_ms=ply_ms, magnet_game_steps_per_s=n / (ply_ms / 1e3),
+               legal_list_ms=list_ms, magnet_policy_ms=magnet_ms, search_policy_ms=search_ms,
+               sample_policy_ms=sample_ms, positions=n,
+               workload=f"{n} games, fused ply with observations and the magnet sampler; "
+                        "policy kernels on the resulting positions")
+    print(f"[bench] policies: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,7 +303,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-history", action="store_true")
+    ap.add_argument("--no-extras", "--no-history", dest="no_history", action="store_true",
+                    help="skip the rollout-buffer, two-square and policy legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--tiling", default=None,
@@ -368,6 +417,8 @@ def main():
     rollout_buffer = None if args.no_history else rollout_buffer_bench(E, torch, n)
     torch.cuda.empty_cache()
     two_square = None if args.no_history else two_square_bench(E, torch, n)
+    torch.cuda.empty_cache()
+    policies = None if args.no_history else policy_bench(E, torch, n)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -405,6 +456,7 @@ def main():
         "serving": serving,
         "rollout_buffer": rollout_buffer,
         "two_square_rule": two_square,
+        "policies": policies,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }
