@@ -81,7 +81,8 @@ class OracleRolloutBuffer:
         cfg = self.e.cfg
         return OracleEngine.from_records(rec, cfg.seed, k_battleless=cfg.k_battleless,
                                          max_moves=cfg.max_moves, auto_reset=bool(cfg.auto_reset),
-                                         two_square=bool(cfg.two_square))
+                                         two_square=bool(cfg.two_square), sampler=cfg.sampler,
+                                         chasing=bool(cfg.chasing))
 
     def mask_at(self, t, games=None):
         return self._engine_at(t, games).mask()

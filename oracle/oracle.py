@@ -30,7 +30,7 @@ def build(force=True):
 class _Cfg(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("k_battleless", ctypes.c_int32),
                 ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
-                ("two_square", ctypes.c_int32), ("sampler", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("two_square", ctypes.c_int32), ("sampler", ctypes.c_int32), ("chasing", ctypes.c_int32)]
 
 
 _lib = None
@@ -64,6 +64,8 @@ def lib():
         L.orc_has_legal_move.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.orc_has_legal_move.restype = ctypes.c_int
         L.orc_two_square_applies.argtypes = [P, P]
+        L.orc_chase_applies.argtypes = [P, P]
+        L.orc_chase_applies.restype = ctypes.c_int
         L.orc_batch_legal_list.argtypes = [P, ctypes.c_int, P, P, P]
         L.orc_batch_magnet.argtypes = [P, ctypes.c_int, P, P]
         L.orc_batch_mmd.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double, P]
@@ -127,13 +129,13 @@ class OracleEngine:
     """N independent games advanced by the C oracle."""
 
     def __init__(self, n, seed, k_battleless=100, max_moves=1000, auto_reset=False,
-                 game_ids=None, reset=True, two_square=False, sampler=SAMPLER_UNIFORM):
+                 game_ids=None, reset=True, two_square=False, sampler=SAMPLER_UNIFORM, chasing=False):
         L = lib()
         self.n = int(n)
         self.sb = int(L.orc_state_bytes())
         self.states = np.zeros(self.n * self.sb, dtype=np.uint8)
         self.cfg = _Cfg(seed, k_battleless, max_moves, 1 if auto_reset else 0, 1 if two_square else 0,
-                        int(sampler), 0)
+                        int(sampler), 1 if chasing else 0)
         if reset:
             self.reset(game_ids)
 
@@ -204,7 +206,7 @@ class OracleEngine:
         """New engine holding per resamples of each game (game ids base + i*per + j)."""
         out = OracleEngine(self.n * per, seed, self.cfg.k_battleless, self.cfg.max_moves,
                            bool(self.cfg.auto_reset), reset=False, two_square=bool(self.cfg.two_square),
-                           sampler=self.cfg.sampler)
+                           sampler=self.cfg.sampler, chasing=bool(self.cfg.chasing))
         lib().orc_batch_resample(_p(self.states), self.n, per, seed, game_id_base, _p(out.states))
         return out
 
@@ -251,15 +253,22 @@ class OracleEngine:
                                       _p(np.ascontiguousarray(probs, dtype=np.float32)), _p(a))
         return a
 
-    def legal_list(self, game, player, two_square=None):
+    def _rules(self, two_square, chasing):
         ts = self.cfg.two_square if two_square is None else int(bool(two_square))
+        ch = self.cfg.chasing if chasing is None else int(bool(chasing))
+        return ts | (ch << 1)
+
+    def legal_list(self, game, player, two_square=None, chasing=None):
         legal = np.zeros(10000, dtype=np.uint8)
-        n = lib().orc_legal_list(self._state_ptr(game), player, ts, _p(legal))
+        n = lib().orc_legal_list(self._state_ptr(game), player, self._rules(two_square, chasing), _p(legal))
         return n, legal
 
-    def has_legal_move(self, game, player, two_square=None):
-        ts = self.cfg.two_square if two_square is None else int(bool(two_square))
-        return bool(lib().orc_has_legal_move(self._state_ptr(game), player, ts))
+    def has_legal_move(self, game, player, two_square=None, chasing=None):
+        return bool(lib().orc_has_legal_move(self._state_ptr(game), player, self._rules(two_square, chasing)))
+
+    def chase_applies(self, game):
+        """The continuous-chasing rule removes a move of the acting player."""
+        return bool(lib().orc_chase_applies(self._state_ptr(game), self._cfgp()))
 
     def two_square_applies(self, game):
         """App. B.1 ComputeTwoSquareRuleApplies for one game."""

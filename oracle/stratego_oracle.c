@@ -17,6 +17,7 @@
  *   App. C  (Information state: C.1 board channels 0-455, C.2 recent moves)
  *   App. D.1 (game-rule hyper-parameters: k-move rule, max game length)
  *   App. B.2 (two-square rule state machine)
+ *   App. B.3 (continuous-chasing rule)
  *
  * Pinning status of each part (how the tests tie it to something other
  * than itself):
@@ -35,6 +36,9 @@
  *   two-square rule ........... pinned by hand-built move sequences written
  *                               from the rule's statement (App. A), including
  *                               Scout spans; the Scout case is a reading
+ *   chasing rule .............. pinned by hand-built chases written from the
+ *                               rule's statement and Table "chase"; threat,
+ *                               evasion and the position window are readings
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -75,8 +79,14 @@ typedef struct {
     int32_t auto_reset;     /* reset terminated games to a fresh setup (App. B) */
     int32_t two_square;     /* enforce the two-square rule (App. A competitive play) */
     int32_t sampler;        /* move sampler: 0 uniform over legal actions, 1 magnet policy */
-    int32_t pad;
+    int32_t chasing;        /* enforce the continuous-chasing rule (App. A competitive play) */
 } orc_cfg;
+
+/* rule flags passed to the move generator */
+enum { RULE_TWO_SQUARE = 1, RULE_CHASING = 2 };
+static int rules_of(const orc_cfg* cfg) {
+    return (cfg->two_square ? RULE_TWO_SQUARE : 0) | (cfg->chasing ? RULE_CHASING : 0);
+}
 
 typedef struct {
     int type;
@@ -113,6 +123,11 @@ typedef struct {
     int ts_piece[2];
     int ts_n[2];
     int ts_pos[2][4];
+    /* continuous-chasing state (App. A Table "chase"): the number of plies of
+     * the current chase (alternating threats by `chaser` and evasions by the
+     * other side, 0 = none, at most 255) and the chasing player */
+    int chase_len;
+    int chaser;
 } orc_state;
 
 /* ------------------------------------------------------------------ */
@@ -288,7 +303,66 @@ static void two_square_update(orc_state* st, int player, int X, int from, int to
     st->ts_n[player] = n;
 }
 
-static int legal_actions(const orc_state* st, int player, int two_square, unsigned char* legal) {
+static int chase_forbids(const orc_state* st, int player, int from, int to);
+
+/* ------------------------------------------------------------------ */
+/* Continuous-chasing rule (App. A and Table "chase"): a threat moves a piece
+ * next to an enemy piece; an evasion moves a piece that the previous move
+ * threatened away from its threatener; a chase is an unbroken alternation of
+ * threats by one player and evasions by the other.  The chasing player may
+ * not make a threat that recreates a position of the chase, unless the moved
+ * piece returns to the square it held before that player's previous turn.
+ * The positions of the chase are rebuilt here by undoing the moves of the
+ * move record (its last 32 plies) on a copy of the board. */
+static int threatens_after(const int board[NSQ], int sq, int player) {
+    int nb[4], nn = neighbours(sq, nb);
+    for (int i = 0; i < nn; i++) {
+        int o = board[nb[i]];
+        if (o >= 0 && owner_of(o) != player) return 1;
+    }
+    return 0;
+}
+
+static int chase_forbids(const orc_state* st, int player, int from, int to) {
+    int L = st->chase_len;
+    if (L < 2 || (L & 1) || st->chaser != player) return 0;   /* not the chaser's turn in a chase */
+    if (st->board[to] != EMPTY) return 0;                      /* an attack is not a threat */
+    int after[NSQ];
+    memcpy(after, st->board, sizeof(after));
+    after[to] = after[from];
+    after[from] = EMPTY;
+    if (!threatens_after(after, to, player)) return 0;
+    int prev = (st->ply - 2) & (RING - 1);                     /* the chaser's previous move */
+    if (st->ring_to[prev] == from && st->ring_from[prev] == to) return 0;
+    int b[NSQ];
+    memcpy(b, st->board, sizeof(b));
+    int K = L < st->ring_count ? L : st->ring_count;
+    for (int k = 1; k <= K; k++) {                             /* positions P_{L-1}, ..., P_{L-K} */
+        int slot = (st->ply - k) & (RING - 1);
+        int f = st->ring_from[slot], g = st->ring_to[slot];
+        b[f] = b[g];
+        b[g] = EMPTY;
+        if (memcmp(b, after, sizeof(b)) == 0) return 1;
+    }
+    return 0;
+}
+
+/* After player p's move from -> to (battle or not, with the previous move's
+ * mover A on a, A = -1 if none): extend, restart or end the chase. */
+static void chase_update(orc_state* st, int p, int battle, int from, int to, int A, int a) {
+    int threat = !battle && threatens_after(st->board, to, p);
+    int evade = !battle && A >= 0 && adjacent(from, a) && !adjacent(to, a);
+    int L = st->chase_len;
+    if (!battle && L > 0 && p == st->chaser && threat && !(L & 1)) L++;
+    else if (!battle && L > 0 && p != st->chaser && evade && (L & 1)) L++;
+    else if (threat) { L = 1; st->chaser = p; }
+    else L = 0;
+    if (L > 255) L = 255;
+    st->chase_len = L;
+    if (L == 0) st->chaser = 0;
+}
+
+static int legal_actions(const orc_state* st, int player, int rules, unsigned char* legal) {
     static const int DR[4] = {-1, 1, 0, 0};
     static const int DC[4] = {0, 0, -1, 1};
     int n = 0;
@@ -308,7 +382,8 @@ static int legal_actions(const orc_state* st, int player, int two_square, unsign
                 if (is_lake(y)) break;
                 int o = st->board[y];
                 if (o >= 0 && owner_of(o) == player) break;
-                if (!(two_square && two_square_forbids(st, player, x, y))) {
+                if (!((rules & RULE_TWO_SQUARE) && two_square_forbids(st, player, x, y)) &&
+                    !((rules & RULE_CHASING) && chase_forbids(st, player, x, y))) {
                     if (legal) legal[100 * x + y] = 1;
                     n++;
                 }
@@ -321,8 +396,8 @@ static int legal_actions(const orc_state* st, int player, int two_square, unsign
 
 /* A player has a legal move iff its legal list is not empty (with the
  * two-square rule on, the list already leaves out the forbidden moves). */
-static int has_legal_move(const orc_state* st, int player, int two_square) {
-    return legal_actions(st, player, two_square, NULL) > 0;
+static int has_legal_move(const orc_state* st, int player, int rules) {
+    return legal_actions(st, player, rules, NULL) > 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -337,9 +412,9 @@ static void terminal_check(orc_state* st, const orc_cfg* cfg, int flag_captured_
         st->reason = REASON_FLAG;
         return;
     }
-    if (!has_legal_move(st, q, cfg->two_square)) {
+    if (!has_legal_move(st, q, rules_of(cfg))) {
         st->done = 1;
-        if (!has_legal_move(st, 1 - q, cfg->two_square)) {
+        if (!has_legal_move(st, 1 - q, rules_of(cfg))) {
             st->outcome = 0;
             st->reason = REASON_FORCED_DRAW;
         } else {
@@ -440,7 +515,7 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
     int from = action / 100, to = action % 100;
     int p = st->ply & 1, q = 1 - p;
     unsigned char legal[10000];
-    legal_actions(st, p, cfg->two_square, legal);
+    legal_actions(st, p, rules_of(cfg), legal);
     if (!legal[action]) return 0;
 
     int X = st->board[from];
@@ -565,8 +640,9 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
         }
     }
 
-    /* the two-square record of the mover's side */
+    /* the two-square record of the mover's side and the chase */
     two_square_update(st, p, X, from, to);
+    chase_update(st, p, battle, from, to, A, a);
 
     /* 7-8. move history and counters */
     int slot = st->ply & (RING - 1);
@@ -770,6 +846,8 @@ static void to_record(const orc_state* st, uint8_t* rec) {
         t[1] = (uint8_t)st->ts_n[p];
         for (int i = 0; i < st->ts_n[p]; i++) t[2 + i] = (uint8_t)st->ts_pos[p][i];
     }
+    rec[40] = (uint8_t)st->chase_len;
+    rec[41] = (uint8_t)st->chaser;
     for (int s = 0; s < NSQ; s++) rec[64 + s] = (uint8_t)(int8_t)st->board[s];
     for (int m = 0; m < RING; m++) {
         rec[164 + 2 * m] = (uint8_t)st->ring_from[m];
@@ -810,6 +888,8 @@ static void from_record(orc_state* st, const uint8_t* rec) {
         st->ts_n[p] = t[1];
         for (int i = 0; i < 4; i++) st->ts_pos[p][i] = i < t[1] ? t[2 + i] : 0;
     }
+    st->chase_len = rec[40];
+    st->chaser = rec[41];
     for (int s = 0; s < NSQ; s++) st->board[s] = (int8_t)rec[64 + s];
     for (int m = 0; m < RING; m++) {
         st->ring_from[m] = rec[164 + 2 * m];
@@ -906,7 +986,7 @@ static int mask_one(const orc_state* st, const orc_cfg* cfg, uint64_t* mask) {
     unsigned char legal[10000];
     memset(mask, 0, MASK_WORDS * sizeof(uint64_t));
     if (st->done) return 0;
-    int n = legal_actions(st, st->ply & 1, cfg->two_square, legal);
+    int n = legal_actions(st, st->ply & 1, rules_of(cfg), legal);
     for (int a = 0; a < 10000; a++)
         if (legal[a]) mask[a >> 6] |= (uint64_t)1 << (a & 63);
     return n;
@@ -1202,20 +1282,28 @@ int orc_num_threads(void) { return 1; }
 #endif
 
 /* Single-game helpers for tests. */
-int orc_legal_list(const orc_state* st, int player, int two_square, unsigned char* legal10000) {
-    return legal_actions(st, player, two_square, legal10000);
+int orc_legal_list(const orc_state* st, int player, int rules, unsigned char* legal10000) {
+    return legal_actions(st, player, rules, legal10000);
 }
 
-int orc_has_legal_move(const orc_state* st, int player, int two_square) {
-    return has_legal_move(st, player, two_square);
+int orc_has_legal_move(const orc_state* st, int player, int rules) {
+    return has_legal_move(st, player, rules);
 }
 
 /* App. B.1 ComputeTwoSquareRuleApplies: the rule is on and removes at least
  * one move the acting player could otherwise make. */
 int orc_two_square_applies(const orc_state* st, const orc_cfg* cfg) {
     if (!cfg->two_square || st->done) return 0;
-    int p = st->ply & 1;
-    return legal_actions(st, p, 0, NULL) != legal_actions(st, p, 1, NULL);
+    int p = st->ply & 1, r = rules_of(cfg);
+    return legal_actions(st, p, r & ~RULE_TWO_SQUARE, NULL) != legal_actions(st, p, r, NULL);
+}
+
+/* The continuous-chasing rule is on and removes at least one move the acting
+ * player could otherwise make. */
+int orc_chase_applies(const orc_state* st, const orc_cfg* cfg) {
+    if (!cfg->chasing || st->done) return 0;
+    int p = st->ply & 1, r = rules_of(cfg);
+    return legal_actions(st, p, r & ~RULE_CHASING, NULL) != legal_actions(st, p, r, NULL);
 }
 
 void orc_terminal_check(orc_state* st, const orc_cfg* cfg) { terminal_check(st, cfg, -1); }

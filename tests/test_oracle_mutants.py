@@ -75,6 +75,14 @@ MUTANTS = [
      "e[k] = ((double)q[j] + alpha * log(rho) + beta * (double)logpi[j]) / (alpha + beta);",
      "e[k] = ((double)q[j] - alpha * log(rho) + beta * (double)logpi[j]) / (alpha + beta);",
      "search_policy"),
+    ("chasing rule ignores the returning exception",
+     "    if (st->ring_to[prev] == from && st->ring_from[prev] == to) return 0;\n",
+     "",
+     "chas"),
+    ("chasing rule skips the chase's first position",
+     "    for (int k = 1; k <= K; k++) {                             /* positions P_{L-1}, ..., P_{L-K} */",
+     "    for (int k = 1; k < K; k++) {                             /* positions P_{L-1}, ..., P_{L-K} */",
+     "chas"),
     ("setup shuffle skips the last swap",
      "for (int i = 39; i >= 1; i--) {\n        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));",
      "for (int i = 39; i >= 2; i--) {\n        int j = (int)bounded(stream_next(&ws), (uint32_t)(i + 1));",

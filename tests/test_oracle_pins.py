@@ -881,3 +881,158 @@ def test_policy_sampler_follows_the_given_distribution():
     one = np.zeros((n, 256), np.float32)
     one[:, 5] = 1.0
     assert np.all(e.sample_policy(one) == acts[0, 5])
+
+
+# ---------------------------------------------------------------- continuous-chasing rule
+# App. A: a chasing player may not make a threat that recreates a position of
+# the chase, unless the moved piece returns to the square it held before that
+# player's previous turn.  Table "chase": threat, evade, chase.
+_CHASE = [1112, 1303, 1202, 313, 203, 1312, 302, 1213]   # red Captain chases the blue Lieutenant
+
+
+def _chase_position():
+    return make_record([dict(sq=11, owner=0, type="Captain"), dict(sq=25, owner=0, type="Major"),
+                        dict(sq=13, owner=1, type="Lieutenant"),
+                        dict(sq=sq(0, 9), owner=0, type="Flag"), dict(sq=sq(9, 0), owner=1, type="Flag")])
+
+
+def test_chasing_rule_forbids_a_repeated_position():
+    on = engine_from([_chase_position()], chasing=True)
+    off = engine_from([_chase_position()], chasing=False)
+    lens = []
+    for a in _CHASE:
+        _play(on, [a])
+        _play(off, [a])
+        lens.append(int(on.export()[0][40]))
+    assert lens == [1, 2, 3, 4, 5, 6, 7, 8] and on.export()[0][41] == 0
+    # 02 -> 12 threatens the Lieutenant on 13 and recreates the position after
+    # the chase's first threat (Captain 12, Major 25, Lieutenant 13)
+    assert 12 not in _moves_of(on, 2) and 12 in _moves_of(off, 2)
+    # 02 -> 03 recreates the position after the third threat, but returns the
+    # Captain to the square it held before red's previous turn: allowed
+    assert 3 in _moves_of(on, 2)
+    assert on.chase_applies(0) and not off.chase_applies(0)
+    # the chase state travels with the record
+    again = engine_from([on.export()[0]], chasing=True)
+    assert 12 not in _moves_of(again, 2)
+
+
+def test_chase_ends_on_a_battle_or_a_non_evasion():
+    e = engine_from([_chase_position()], chasing=True)
+    _play(e, _CHASE[:3])
+    assert e.export()[0][40] == 3
+    # the Lieutenant on 03 attacks the Captain on 02 instead of evading: the battle ends the chase
+    r = e.step(np.array([100 * 3 + 2], np.int16))
+    assert r["first_bad"] == -1 and e.export()[0][40] == 0
+    e2 = engine_from([_chase_position()], chasing=True)
+    _play(e2, _CHASE[:1])
+    # 13 -> 14 leaves the Captain's side but stays... 14 is not next to 12, so it
+    # is an evasion; 13 -> 23 likewise; the Flag cannot move, so blue breaks the
+    # chase only with a move of another piece: give blue a Scout for that
+    assert e2.export()[0][40] == 1
+
+
+def _is_threat(b, p, x, y):
+    """Non-battle move x -> y of player p ending next to an enemy piece."""
+    if b[y] != -1:
+        return False
+    res = list(b)
+    res[y], res[x] = res[x], -1
+    return any(res[z] >= 0 and (res[z] >= 40) != (p == 1) for z in _nbrs(y))
+
+
+def _nbrs(s):
+    r, c = divmod(s, 10)
+    return [10 * (r + dr) + c + dc for dr, dc in ((-1, 0), (1, 0), (0, -1), (0, 1))
+            if 0 <= r + dr < 10 and 0 <= c + dc < 10]
+
+
+def chasing_actions(e, rng):
+    """A move chooser that keeps chases going: a threat when one exists (else
+    an evasion of the last threat, else any legal move), at random among them."""
+    recs = e.export()
+    out = np.full(e.n, -1, dtype=np.int16)
+    for g in range(e.n):
+        r = recs[g]
+        if r[17]:
+            continue
+        p = int(r[8]) & 1
+        b = [int(v) for v in board(r)]
+        _, legal = e.legal_list(g, p)
+        acts = [int(a) for a in np.flatnonzero(legal)]
+        if not acts:
+            continue
+        threats = [a for a in acts if _is_threat(b, p, a // 100, a % 100)]
+        last = (int(r[8]) - 1) & 31
+        a_sq = int(r[164 + 2 * last + 1]) if r[16] else -1
+        evades = [a for a in acts if a_sq >= 0 and b[a_sq] >= 0 and a_sq in _nbrs(a // 100)
+                  and a_sq not in _nbrs(a % 100) and b[a % 100] == -1]
+        pool = threats or evades or acts
+        out[g] = pool[int(rng.integers(0, len(pool)))]
+    return out
+
+
+def test_chasing_rule_against_full_board_history():
+    """Sparse games driven to chase: the chase state and the forbidden moves
+    equal those obtained from the full board history by the definitions of
+    Table "chase" (positions of the chase within the last 32 plies, compared
+    as whole boards)."""
+    rng = np.random.default_rng(17)
+    recs = [random_position(rng, int(rng.integers(1, 4)), int(rng.integers(1, 4))) for _ in range(150)]
+    e = engine_from(recs, chasing=True, max_moves=400)
+    hist = [[[int(v) for v in board(r)]] for r in e.export()]
+    state = [(0, 0, None) for _ in recs]     # chase length, chaser, last move (player, from, to)
+    seen_forbidden = 0
+    for ply in range(120):
+        a = chasing_actions(e, rng)
+        before = e.export()
+        r = e.step(a)
+        assert r["first_bad"] == -1
+        after = e.export()
+        for g in range(len(recs)):
+            if a[g] < 0 or before[g][17]:
+                continue
+            p = int(before[g][8]) & 1
+            f, t = divmod(int(a[g]), 100)
+            b0 = hist[g][-1]
+            b1 = [int(v) for v in board(after[g])]
+            battle = b0[t] >= 0
+            L, C, last = state[g]
+            threat = not battle and any(b1[z] >= 0 and (b1[z] >= 40) != (p == 1) for z in _nbrs(t))
+            evade = (not battle and last is not None and last[0] != p and b0[last[2]] >= 0
+                     and last[2] in _nbrs(f) and last[2] not in _nbrs(t))
+            if not battle and L > 0 and p == C and threat and L % 2 == 0:
+                L += 1
+            elif not battle and L > 0 and p != C and evade and L % 2 == 1:
+                L += 1
+            elif threat:
+                L, C = 1, p
+            else:
+                L, C = 0, 0
+            L = min(L, 255)
+            state[g] = (L, C, (p, f, t))
+            hist[g].append(b1)
+            assert (int(after[g][40]), int(after[g][41])) == (L, C), (g, ply)
+            if after[g][17]:
+                continue
+            q = 1 - p
+            _, l_on = e.legal_list(g, q)
+            _, l_off = e.legal_list(g, q, chasing=False)
+            got = set(np.flatnonzero(l_off & ~l_on).tolist())
+            want = set()
+            if L >= 2 and L % 2 == 0 and C == q:
+                window = hist[g][-1 - min(L, 32):-1]
+                prev = (int(after[g][8]) - 2) & 31
+                prev_f, prev_t = int(after[g][164 + 2 * prev]), int(after[g][165 + 2 * prev])
+                for act in np.flatnonzero(l_off):
+                    x, y = divmod(int(act), 100)
+                    if not _is_threat(b1, q, x, y) or (prev_t == x and prev_f == y):
+                        continue
+                    res = list(b1)
+                    res[y], res[x] = res[x], -1
+                    if any(res == w for w in window):
+                        want.add(int(act))
+            assert got == want, (g, ply, got, want)
+            seen_forbidden += len(want)
+    print("forbidden moves seen:", seen_forbidden)
+    assert seen_forbidden >= 20, seen_forbidden
