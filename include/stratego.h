@@ -80,6 +80,10 @@ typedef struct {
   int32_t sampler;         /* move sampler of stratego_sample_actions and the fused plies:
                               0 uniform over legal actions; 1 magnet policy (section 2.3: a
                               piece with a legal move uniformly, then one of its moves) */
+  int32_t chasing_rule;    /* 1: continuous-chasing rule (App. A, Table "chase", App. B.3): the
+                              chasing player may not make a threat that recreates a position
+                              of the chase (within the last 32 plies), unless the moved piece
+                              returns to its square before that player's previous turn */
 } stratego_config;
 
 /* Create a context with N games, all reset to fresh setups (episode 0).
@@ -282,6 +286,8 @@ int stratego_history_encode_obs(stratego_ctx* ctx, int64_t t, const int32_t* gam
  *   two_square_applies  uint8: the two-square rule is on and removes at least
  *                              one move the acting player could otherwise make
  *                              (ComputeTwoSquareRuleApplies)
+ *   chase_applies       uint8: the chasing rule is on and removes at least one
+ *                              move the acting player could otherwise make
  *   is_unknown          uint8 [count][100]: 1 on squares holding an opponent
  *                              piece whose type the acting player has not seen
  *                              (ComputeIsUnknownPiece), acting player's frame
@@ -301,6 +307,7 @@ typedef struct {
   uint8_t* is_unknown;
   uint8_t* piece_onehot;
   uint8_t* two_square_applies;
+  uint8_t* chase_applies;
 } stratego_history_outputs;
 int stratego_history_info(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
                           const stratego_history_outputs* out);

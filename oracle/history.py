@@ -103,7 +103,7 @@ class OracleRolloutBuffer:
                    num_moves=np.zeros(m, np.int32), moves_since_attack=np.zeros(m, np.int32),
                    reward_pl0=np.zeros(m, np.int8), terminated_since=np.zeros(m, np.int32),
                    has_legal_movement=np.zeros(m, np.uint8), flag_captured=np.zeros(m, np.uint8),
-                   two_square_applies=np.zeros(m, np.uint8),
+                   two_square_applies=np.zeros(m, np.uint8), chase_applies=np.zeros(m, np.uint8),
                    is_unknown=np.zeros((m, 100), np.uint8), piece_onehot=np.zeros((m, 24, 100), np.uint8))
         row = self.rows.get(t) if t < self.t else None
         for k, g in enumerate(ids):
@@ -128,6 +128,7 @@ class OracleRolloutBuffer:
                 out["terminated_since"][k] = since
             out["has_legal_movement"][k] = int((not done) and eng.has_legal_move(k, p))
             out["two_square_applies"][k] = int(eng.two_square_applies(k))
+            out["chase_applies"][k] = int(eng.chase_applies(k))
             for s in range(100):
                 pid = int(r[_BOARD + s])   # int8 in the record: >= 128 means empty or lake
                 if pid >= 128:

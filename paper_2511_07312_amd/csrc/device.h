@@ -34,6 +34,8 @@ constexpr int kOffOutcome = 18;
 constexpr int kOffReason = 19;
 constexpr int kOffRedraws = 20;
 constexpr int kOffTwoSquare = 24;   // per player p at +8p: u8 piece, u8 n, u8 squares[4]
+constexpr int kOffChaseLen = 40;    // u8 plies of the current chase (0 = none)
+constexpr int kOffChaser = 41;      // u8 chasing player
 constexpr int kOffBoard = 64;
 constexpr int kOffRing = 164;
 constexpr int kOffPieces = 256;
@@ -96,6 +98,7 @@ struct Rules {
   int32_t auto_reset;
   int32_t two_square;   // enforce the two-square rule
   int32_t sampler;      // 0: uniform over legal actions; 1: magnet policy
+  int32_t chasing;      // enforce the continuous-chasing rule
 };
 enum : int { kSamplerUniform = 0, kSamplerMagnet = 1 };
 constexpr int kMaxLegal = 256;   // legal-list capacity (at most 244 legal moves exist)
@@ -359,15 +362,137 @@ __device__ __forceinline__ void two_square_update(uint8_t* R, int p, int X, int 
   }
 }
 
+// ---------------------------------------------------------------- continuous-chasing rule
+// App. A and Table "chase": a threat is a move after which the moved piece
+// stands next to an enemy piece; an evasion moves a piece that the previous
+// move threatened away from its threatener; a chase alternates threats by
+// one player and evasions by the other.  The chasing player may not make a
+// threat that recreates a position of the chase, unless the moved piece
+// returns to the square it held before that player's previous turn.  The
+// chase's positions (within the 32-ply move record) are compared with the
+// current one by their differences: undoing the chase's moves one by one,
+// a position that differs from the current one in a single piece of the
+// chaser, standing on square s, forbids that piece's move to s.
+// Work area (per wave, 160 bytes of LDS): displaced pieces, their current
+// squares, their squares in the rebuilt position, and the forbidden moves.
+constexpr int kWorkPiece = 0, kWorkCur = 32, kWorkAt = 64, kWorkFrom = 96, kWorkTo = 128;
+
+__device__ __forceinline__ bool chase_active(const uint8_t* R, int p) {
+  const int L = R[kOffChaseLen];
+  return L >= 2 && (L & 1) == 0 && R[kOffChaser] == p;
+}
+
+// Single lane: writes the forbidden (from, to) pairs to the work area and
+// returns their number.
+__device__ __forceinline__ int chase_forbidden_list(const uint8_t* R, int p, uint8_t* work) {
+  if (!chase_active(R, p)) return 0;
+  const int ply = (int)hdr_u32(R, kOffPly), rc = R[kOffRingCount], L = R[kOffChaseLen];
+  const int K = L < rc ? L : rc;
+  const int pslot = (ply - 2) & 31;
+  const int prev_from = R[kOffRing + 2 * pslot], prev_to = R[kOffRing + 2 * pslot + 1];
+  uint8_t* pc = work + kWorkPiece;
+  uint8_t* cur = work + kWorkCur;
+  uint8_t* at = work + kWorkAt;
+  int ne = 0, ndiff = 0, nf = 0;
+  for (int k = 1; k <= K; ++k) {
+    const int slot = (ply - k) & 31;
+    const int f = R[kOffRing + 2 * slot], g = R[kOffRing + 2 * slot + 1];
+    int e = -1;
+    for (int i = 0; i < ne; ++i)
+      if (at[i] == g) { e = i; break; }
+    if (e < 0) {   // the mover of that ply is still on g now
+      const int id = board_at(R, g);
+      if (id < 0) break;
+      e = ne++;
+      pc[e] = (uint8_t)id;
+      cur[e] = (uint8_t)g;
+      at[e] = (uint8_t)g;
+    }
+    ndiff -= at[e] != cur[e];
+    at[e] = (uint8_t)f;
+    ndiff += at[e] != cur[e];
+    if (ndiff != 1) continue;
+    int x = -1, sq = -1, id = -1;
+    for (int i = 0; i < ne; ++i)
+      if (at[i] != cur[i]) { x = cur[i]; sq = at[i]; id = pc[i]; }
+    if (owner(id) != p || (prev_to == x && prev_from == sq)) continue;
+    bool threat = false;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int y = neighbour(sq, d);
+      if (y < 0 || y == x) continue;
+      const int o = board_at(R, y);
+      if (o >= 0 && owner(o) != p) threat = true;
+    }
+    if (!threat) continue;
+    work[kWorkFrom + nf] = (uint8_t)x;
+    work[kWorkTo + nf] = (uint8_t)sq;
+    ++nf;
+  }
+  return nf;
+}
+
+// Single lane, after player p's move from -> to (A: the previous move's
+// mover still on its destination a, or -1): extend, restart or end the chase.
+__device__ __forceinline__ void chase_update(uint8_t* R, int p, bool battle, int from, int to, int A, int a) {
+  bool threat = false;
+  if (!battle) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int y = neighbour(to, d);
+      if (y < 0) continue;
+      const int o = board_at(R, y);
+      if (o >= 0 && owner(o) != p) threat = true;
+    }
+  }
+  const bool evade = !battle && A >= 0 && adjacent(from, a) && !adjacent(to, a);
+  int L = R[kOffChaseLen];
+  const int C = R[kOffChaser];
+  if (!battle && L > 0 && p == C && threat && (L & 1) == 0) ++L;
+  else if (!battle && L > 0 && p != C && evade && (L & 1) == 1) ++L;
+  else if (threat) { L = 1; R[kOffChaser] = (uint8_t)p; }
+  else L = 0;
+  R[kOffChaseLen] = (uint8_t)(L > 255 ? 255 : L);
+  if (L == 0) R[kOffChaser] = 0;
+}
+
 // True when player p owns a movable piece with an adjacent empty or enemy
 // square, i.e. p has at least one legal move (with the two-square rule, the
 // tracked piece counts only through its allowed moves).
-__device__ __forceinline__ bool has_move(const uint8_t* R, int p, bool two_square) {
+__device__ __forceinline__ bool has_move(const uint8_t* R, int p, Rules rules, uint8_t* work) {
   const int lane = lane_id();
   // the piece the two-square rule may restrict: it counts only through its
   // allowed moves (tested below); -1 when none
   const uint8_t* t = R + kOffTwoSquare + 8 * p;
-  const int rx = __builtin_amdgcn_readfirstlane(two_square && t[1] == 4 ? (int)t[5] : -1);
+  const int rx = __builtin_amdgcn_readfirstlane(rules.two_square && t[1] == 4 ? (int)t[5] : -1);
+  if (rules.chasing && chase_active(R, p)) {
+    // the chasing rule may forbid some threats: count the moves that remain
+    int nf = 0;
+    if (lane == 0) nf = chase_forbidden_list(R, p, work);
+    nf = __shfl(nf, 0, 64);
+    wave_sync();
+    if (nf > 0) {
+      int x2, axis, L, H;
+      const bool window = rx >= 0 && two_square_window(R, p, x2, axis, L, H);
+      bool any = false;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int x = lane + 64 * h;
+        if (x >= kSquares) break;
+        uint64_t lo, hi;
+        destinations(R, x, p, lo, hi);
+        if (window && x == rx) two_square_clear(x, axis, L, H, lo, hi);
+        for (int i = 0; i < nf; ++i) {
+          if (work[kWorkFrom + i] != x) continue;
+          const int y = work[kWorkTo + i];
+          if (y < 64) lo &= ~(1ull << y);
+          else hi &= ~(1ull << (y - 64));
+        }
+        if (lo | hi) any = true;
+      }
+      return ballot(any) != 0;
+    }
+  }
   bool any = false;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -427,7 +552,9 @@ __device__ __forceinline__ bool action_is_legal(const uint8_t* R, int p, int act
 // Mask words of the acting player: lane l returns words l, 64+l, 128+l (the
 // last only for l < 29).  ts is the LDS array of 100 destination sets
 // (2 x u64 each).  Returns the number of legal actions (wave-uniform).
-__device__ __forceinline__ int legal_mask_words(const uint8_t* R, uint64_t* ts, uint64_t w[3], bool two_square) {
+__device__ __forceinline__ int legal_mask_words(const uint8_t* R, uint64_t* ts, uint64_t w[3], Rules rules,
+                                                uint8_t* work) {
+  const bool two_square = rules.two_square;
   const int lane = lane_id();
   const int p = hdr_u32(R, kOffPly) & 1;
   const bool done = R[kOffDone] != 0;
@@ -455,6 +582,18 @@ __device__ __forceinline__ int legal_mask_words(const uint8_t* R, uint64_t* ts, 
       ts[2 * rx] = lo;
       ts[2 * rx + 1] = hi;
       cnt -= before - (__popcll(lo) + __popcll(hi));
+    }
+    wave_sync();
+  }
+  if (rules.chasing && !done && chase_active(R, p)) {
+    if (lane == 0) {
+      const int nf = chase_forbidden_list(R, p, work);
+      for (int i = 0; i < nf; ++i) {
+        const int x = work[kWorkFrom + i], y = work[kWorkTo + i];
+        uint64_t& set = ts[2 * x + (y >= 64)];
+        const uint64_t bit = 1ull << (y & 63);
+        if (set & bit) { set &= ~bit; --cnt; }
+      }
     }
     wave_sync();
   }
@@ -562,15 +701,15 @@ __device__ __forceinline__ void square_set_from_mask(const uint64_t* mask, int x
 // App. A: capture of the flag wins; a player to move without legal moves loses,
 // a draw when neither side can move; App. D.1: k-move rule, maximum length.
 // Priority: flag > no moves > k-move > max moves.  Writes done/outcome/reason.
-__device__ __forceinline__ void terminal_check(uint8_t* R, Rules rules, int flag_winner) {
+__device__ __forceinline__ void terminal_check(uint8_t* R, Rules rules, int flag_winner, uint8_t* work) {
   const int ply = (int)hdr_u32(R, kOffPly);
   const int q = ply & 1;
   int done = 0, outcome = 0, reason = kReasonNone;
   if (flag_winner >= 0) {
     done = 1; outcome = flag_winner == 0 ? 1 : -1; reason = kReasonFlag;
-  } else if (!has_move(R, q, rules.two_square)) {
+  } else if (!has_move(R, q, rules, work)) {
     done = 1;
-    if (!has_move(R, 1 - q, rules.two_square)) { outcome = 0; reason = kReasonForcedDraw; }
+    if (!has_move(R, 1 - q, rules, work)) { outcome = 0; reason = kReasonForcedDraw; }
     else { outcome = (1 - q) == 0 ? 1 : -1; reason = kReasonForcedWin; }
   } else if ((int)hdr_u32(R, kOffBattleless) >= rules.k_battleless) {
     done = 1; reason = kReasonKMove;
@@ -646,10 +785,13 @@ __device__ __forceinline__ void fresh_setup(uint8_t* R, uint8_t* scratch, uint64
   wave_sync();
 }
 
-__device__ __forceinline__ void reset_game(uint8_t* R, uint8_t* scratch, Rules rules, uint32_t game_id,
+__device__ __forceinline__ void reset_game(uint8_t* R, uint8_t* scratch, uint8_t* work, Rules rules, uint32_t game_id,
                            uint32_t episode, uint32_t redraws) {
+  // a fresh setup has no move history, so neither competitive rule can bite
+  rules.two_square = 0;
+  rules.chasing = 0;
   fresh_setup(R, scratch, rules.seed, game_id, episode, redraws);
-  terminal_check(R, rules, -1);
+  terminal_check(R, rules, -1, work);
   // A setup that is already terminal is replaced by the next episode's setup
   // (probability ~4e-6 per game); the bound only guards against a hang.
   int guard = 0;
@@ -658,7 +800,7 @@ __device__ __forceinline__ void reset_game(uint8_t* R, uint8_t* scratch, Rules r
     ++redraws;
     ++guard;
     fresh_setup(R, scratch, rules.seed, game_id, episode, redraws);
-    terminal_check(R, rules, -1);
+    terminal_check(R, rules, -1, work);
   }
 }
 
@@ -671,7 +813,7 @@ __device__ __forceinline__ void reset_game(uint8_t* R, uint8_t* scratch, Rules r
 // non-battle reply to a threat in which the mover newly becomes adjacent to a
 // square next to the threatener).  Then pushes the move into the ring,
 // advances the counters and runs the terminal check.
-__device__ __forceinline__ void apply_action(uint8_t* R, Rules rules, int action) {
+__device__ __forceinline__ void apply_action(uint8_t* R, Rules rules, int action, uint8_t* work) {
   const int lane = lane_id();
   const int from = action / 100, to = action - 100 * (action / 100);
   const int ply = (int)hdr_u32(R, kOffPly);
@@ -797,8 +939,9 @@ __device__ __forceinline__ void apply_action(uint8_t* R, Rules rules, int action
         }
       }
     }
-    // the two-square record of the mover's side
+    // the two-square record of the mover's side and the chase
     two_square_update(R, p, X, from, to);
+    chase_update(R, p, battle, from, to, A, a);
     // 7-8. ring and counters
     const int slot = ply & 31;
     R[kOffRing + 2 * slot] = (uint8_t)from;
@@ -809,7 +952,7 @@ __device__ __forceinline__ void apply_action(uint8_t* R, Rules rules, int action
   }
   flag_winner = __shfl(flag_winner, 0, 64);
   wave_sync();
-  terminal_check(R, rules, flag_winner);
+  terminal_check(R, rules, flag_winner, work);
 }
 
 struct StepOut {
@@ -821,31 +964,38 @@ struct StepOut {
 // validate: check the action against the rules first (caller-supplied
 // actions); actions drawn from the legal mask skip the check.
 template <bool validate>
-__device__ __forceinline__ StepOut step_game(uint8_t* R, uint8_t* scratch, Rules rules, int action) {
+__device__ __forceinline__ StepOut step_game(uint8_t* R, uint8_t* scratch, uint8_t* work, Rules rules, int action) {
   StepOut o{0, 0, 0, 0, false};
+  const bool was_done = R[kOffDone] != 0;
+  if (!was_done) {
+    if (action == -1) return o;
+    if (validate) {
+      const int p = hdr_u32(R, kOffPly) & 1;
+      bool ok = action_is_legal(R, p, action, rules.two_square);
+      if (ok && rules.chasing && chase_active(R, p)) {
+        int nf = 0;
+        if (lane_id() == 0) nf = chase_forbidden_list(R, p, work);
+        nf = __shfl(nf, 0, 64);
+        wave_sync();
+        for (int i = 0; i < nf; ++i)
+          if (work[kWorkFrom + i] == action / 100 && work[kWorkTo + i] == action % 100) ok = false;
+      }
+      if (!ok) {
+        o.illegal = true;
+        return o;
+      }
+    }
+    apply_action(R, rules, action, work);
+  }
+  // a game that was over already, or ended now, reports its episode and,
+  // with auto-reset, restarts with the next one
   if (R[kOffDone]) {
     o.done = 1;
     o.outcome = (int8_t)R[kOffOutcome];
     o.reason = R[kOffReason];
     o.ep_len = (int)hdr_u32(R, kOffPly);
     if (rules.auto_reset)
-      reset_game(R, scratch, rules, hdr_u32(R, kOffGameId), hdr_u32(R, kOffEpisode) + 1,
-                 hdr_u32(R, kOffRedraws));
-    return o;
-  }
-  if (action == -1) return o;
-  if (validate && !action_is_legal(R, hdr_u32(R, kOffPly) & 1, action, rules.two_square)) {
-    o.illegal = true;
-    return o;
-  }
-  apply_action(R, rules, action);
-  if (R[kOffDone]) {
-    o.done = 1;
-    o.outcome = (int8_t)R[kOffOutcome];
-    o.reason = R[kOffReason];
-    o.ep_len = (int)hdr_u32(R, kOffPly);
-    if (rules.auto_reset)
-      reset_game(R, scratch, rules, hdr_u32(R, kOffGameId), hdr_u32(R, kOffEpisode) + 1,
+      reset_game(R, scratch, work, rules, hdr_u32(R, kOffGameId), hdr_u32(R, kOffEpisode) + 1,
                  hdr_u32(R, kOffRedraws));
   }
   return o;
@@ -1369,6 +1519,8 @@ __device__ __forceinline__ bool record_ok(const uint8_t* R) {
       (int)hdr_u32(R, kOffPly) < 0 || (int)hdr_u32(R, kOffPly) > 32767 ||
       (int)hdr_u32(R, kOffBattleless) < 0)
     bad = true;
+  // chase: a chasing player only while a chase lasts
+  if (R[kOffChaser] > 1 || (R[kOffChaseLen] == 0 && R[kOffChaser] != 0)) bad = true;
   // two-square records: 0 or 2-4 squares on the board, of a piece id of that
   // player, unused bytes zero
   if (lane < 2) {

@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       int action = -1;
       if (MODE & kDoMask) {
         uint64_t w[3];
-        const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules.two_square);
+        const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
         fetch_next();
         if (a.mask) {
           uint64_t* m = a.mask + (size_t)oi * kMaskWords;
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       }
       if (MODE & kDoStep) {
         if (a.hist) store_record(a.hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
-        StepOut o = step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, a.rules, action);
+        StepOut o = step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, slab + kSlabProbQ, a.rules, action);
         if (lane == 0) {
           const size_t row = (size_t)a.out_base + oi;
           if (a.done) a.done[row] = (int8_t)o.done;
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256) k_reset_fresh(uint8_t* states, const int3
     if (lane_id() == 0) atomicMin(&err[1], i);
     return;
   }
-  reset_game(slab, slab + kSlabScratch, rules, game_id_base + (uint32_t)slot, 0u, 0u);
+  reset_game(slab, slab + kSlabScratch, slab + kSlabProbQ, rules, game_id_base + (uint32_t)slot, 0u, 0u);
   store_record(states + (size_t)slot * kRecordBytes, slab);
 }
 
@@ -381,7 +381,7 @@ struct HistArgs {
 __host__ __device__ __forceinline__ constexpr int hist_lds_bytes(int q) {
   return q == kQObs ? slab_bytes_for(kLayoutBits)
        : q == kQMask ? kSlabImage + kDestSetBytes
-       : q == kQInfo ? kRecordBytes : 16;
+       : q == kQInfo ? kSlabImage : 16;
 }
 
 template <int Q>
@@ -405,7 +405,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
   load_record(R, src);
   if (Q == kQMask) {
     uint64_t w[3];
-    const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, h.rules.two_square);
+    const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, h.rules, slab + kSlabProbQ);
     if (h.mask) {
       uint64_t* m = h.mask + (size_t)i * kMaskWords;
 #pragma unroll
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
     const stratego_history_outputs& o = h.out;
     const int ply = (int)hdr_u32(R, kOffPly), p = ply & 1;
     const bool done = R[kOffDone] != 0;
-    const bool movable = has_move(R, p, h.rules.two_square) && !done;   // wave-wide
+    const bool movable = has_move(R, p, h.rules, slab + kSlabProbQ) && !done;   // wave-wide
     // per-square views in the acting player's frame
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -479,6 +479,23 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
         }
         o.two_square_applies[i] = (uint8_t)applies;
       }
+      if (o.chase_applies) {   // the chasing rule removes a move the acting player could otherwise make
+        bool applies = false;
+        if (h.rules.chasing && !done && chase_active(R, p)) {
+          uint8_t* work = slab + kSlabProbQ;
+          const int nf = chase_forbidden_list(R, p, work);
+          for (int k = 0; k < nf && !applies; ++k) {
+            uint64_t lo, hi;
+            const int x = work[kWorkFrom + k], y = work[kWorkTo + k];
+            destinations(R, x, p, lo, hi);
+            int x2, axis, L, H;
+            if (h.rules.two_square && two_square_window(R, p, x2, axis, L, H) && x2 == x)
+              two_square_clear(x, axis, L, H, lo, hi);
+            applies = ((y < 64 ? lo >> y : hi >> (y - 64)) & 1) != 0;
+          }
+        }
+        o.chase_applies[i] = (uint8_t)applies;
+      }
     }
   }
 }
@@ -528,7 +545,7 @@ __global__ void __launch_bounds__(256) k_policy(PolicyArgs a) {
   load_record(R, a.states + (size_t)i * kRecordBytes);
   const uint64_t* ts = reinterpret_cast<const uint64_t*>(slab + kSlabImage);
   uint64_t w[3];
-  const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules.two_square);
+  const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
   // the legal list, ascending: word order, then bit order
   int16_t* list = reinterpret_cast<int16_t*>(slab + kPolicyList);
   int base = 0;
@@ -653,6 +670,7 @@ inline Rules rules_of(const stratego_ctx* c) {
   r.auto_reset = c->cfg.auto_reset;
   r.two_square = c->cfg.two_square_rule;
   r.sampler = c->cfg.sampler;
+  r.chasing = c->cfg.chasing_rule;
   return r;
 }
 
@@ -808,7 +826,8 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
   if (cfg->num_games <= 0 || cfg->k_battleless <= 0 || cfg->max_moves <= 0 ||
       cfg->max_moves > 32767 || (cfg->auto_reset != 0 && cfg->auto_reset != 1) ||
       (cfg->two_square_rule != 0 && cfg->two_square_rule != 1) ||
-      (cfg->sampler != kSamplerUniform && cfg->sampler != kSamplerMagnet))
+      (cfg->sampler != kSamplerUniform && cfg->sampler != kSamplerMagnet) ||
+      (cfg->chasing_rule != 0 && cfg->chasing_rule != 1))
     return STRATEGO_E_INVAL;
   int G = cfg->games_per_wg ? cfg->games_per_wg : 1;
   int S = cfg->lds_layout ? cfg->lds_layout : kLayoutBits;

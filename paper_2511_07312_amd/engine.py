@@ -49,14 +49,14 @@ class StrategoConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("game_id_base", ctypes.c_uint32),
                 ("games_per_wg", ctypes.c_int32), ("lds_layout", ctypes.c_int32),
                 ("history_len", ctypes.c_int32), ("two_square_rule", ctypes.c_int32),
-                ("sampler", ctypes.c_int32)]
+                ("sampler", ctypes.c_int32), ("chasing_rule", ctypes.c_int32)]
 
 
 class HistoryOutputs(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in (
         "acting_player", "played_action", "num_moves", "moves_since_attack", "reward_pl0",
         "terminated_since", "has_legal_movement", "flag_captured", "is_unknown", "piece_onehot",
-        "two_square_applies")]
+        "two_square_applies", "chase_applies")]
 
 
 # dtype and elements per listed game of each history_info output
@@ -66,7 +66,7 @@ HISTORY_INFO = {
     "reward_pl0": (torch.int8, 1), "terminated_since": (torch.int32, 1),
     "has_legal_movement": (torch.uint8, 1), "flag_captured": (torch.uint8, 1),
     "is_unknown": (torch.uint8, 100), "piece_onehot": (torch.uint8, 2400),
-    "two_square_applies": (torch.uint8, 1),
+    "two_square_applies": (torch.uint8, 1), "chase_applies": (torch.uint8, 1),
 }
 
 
@@ -175,10 +175,10 @@ def _stream():
 # ------------------------------------------------------------------ C-ABI mirrors
 def stratego_init(num_games, seed, k_battleless=100, max_moves=4000, auto_reset=False,
                   game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, two_square=False,
-                  sampler=SAMPLER_UNIFORM):
+                  sampler=SAMPLER_UNIFORM, chasing=False):
     cfg = StrategoConfig(int(num_games), int(k_battleless), int(max_moves), int(bool(auto_reset)),
                          int(seed), int(game_id_base), int(games_per_wg), int(lds_layout),
-                         int(history_len), int(bool(two_square)), int(sampler))
+                         int(history_len), int(bool(two_square)), int(sampler), int(bool(chasing)))
     ctx = ctypes.c_void_p()
     _check(load_library().stratego_init(ctypes.byref(cfg), _stream(), ctypes.byref(ctx)),
            "stratego_init")
@@ -414,11 +414,12 @@ class Engine:
 
     def __init__(self, num_games, seed, k_battleless=100, max_moves=1000, auto_reset=False,
                  game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, two_square=False,
-                 sampler=SAMPLER_UNIFORM, device="cuda"):
+                 sampler=SAMPLER_UNIFORM, chasing=False, device="cuda"):
         self.n = int(num_games)
         self.device = torch.device(device)
         self.ctx = stratego_init(num_games, seed, k_battleless, max_moves, auto_reset,
-                                 game_id_base, games_per_wg, lds_layout, history_len, two_square, sampler)
+                                 game_id_base, games_per_wg, lds_layout, history_len, two_square, sampler,
+                                 chasing)
         n, d = self.n, self.device
         self.mask = torch.empty((n, MASK_WORDS), dtype=torch.int64, device=d)
         self.num_legal = torch.empty(n, dtype=torch.int16, device=d)

@@ -1,6 +1,7 @@
-"""The two-square rule (App. A competitive play, App. B.2) on the GPU vs the
-oracle, bit-exact: masks, sampled actions, outcomes, records (which carry the
-rule's state) and ComputeTwoSquareRuleApplies."""
+"""The competitive-play rules (App. A) on the GPU vs the oracle, bit-exact:
+the two-square rule (App. B.2) and the continuous-chasing rule (Table
+"chase", App. B.3) in masks, sampled and caller actions, outcomes, records
+(which carry both rules' state) and the rule-applies queries."""
 import numpy as np
 import pytest
 
@@ -129,3 +130,83 @@ def test_dead_end_loss_matches_the_oracle():
         assert int(eng.done[0]) == (1 if rule else 0)
         assert eng.error() == (0, -1)
         eng.close()
+
+
+# ---------------------------------------------------------------- continuous-chasing rule
+def test_chase_driven_games_match_the_oracle():
+    """Sparse games whose moves keep chases going (threats first, then
+    evasions): chase state, masks, outcomes and records bit-exact, the
+    caller actions validated by the kernels, the rule biting many times."""
+    from test_oracle_pins import chasing_actions, random_position
+    rng = np.random.default_rng(23)
+    recs = np.stack([random_position(rng, int(rng.integers(1, 4)), int(rng.integers(1, 4)))
+                     for _ in range(400)])
+    n, seed = len(recs), 4
+    kw = dict(k_battleless=100, max_moves=400, auto_reset=False, chasing=True)
+    eng = E.Engine(n, seed, **kw)
+    eng.load(torch.from_numpy(recs).cuda())
+    ref = O.OracleEngine.from_records(recs, seed, **kw)
+    applies = torch.empty(n, dtype=torch.uint8, device="cuda")
+    bites = 0
+    for ply in range(100):
+        E.stratego_history_info(eng.ctx, eng.window()[1], None, n, chase_applies=applies)
+        want = np.array([ref.chase_applies(g) for g in range(n)], dtype=np.uint8)
+        assert_same(f"chase applies@{ply}", cpu(applies), want)
+        bites += int(want.sum())
+        eng.legal_mask()
+        m, nl = ref.mask()
+        assert_same(f"mask@{ply}", cpu(eng.mask), m)
+        a = chasing_actions(ref, rng)
+        r = ref.step(a)
+        eng.step(torch.from_numpy(a).cuda())
+        for k in ("done", "outcome", "reason", "ep_len"):
+            assert_same(f"{k}@{ply}", cpu(getattr(eng, k)), r[k])
+        assert_same(f"states@{ply}", cpu(eng.export()), ref.export())
+    assert bites >= 50, bites
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
+def test_chase_scenario_and_forbidden_caller_action():
+    from test_oracle_pins import _CHASE, _chase_position
+    rec = _chase_position()
+    eng = E.Engine(1, 1, chasing=True)
+    eng.load(torch.from_numpy(rec[None]).cuda())
+    for a in _CHASE:
+        E.stratego_step(eng.ctx, torch.tensor([a], dtype=torch.int16, device="cuda"))
+    assert eng.error() == (0, -1)
+    st = cpu(eng.export())[0]
+    assert int(st[40]) == 8 and int(st[41]) == 0
+    eng.legal_mask()
+    m = cpu(eng.mask)[0]
+    bit = lambda act: (int(m[act >> 6]) >> (act & 63)) & 1
+    assert bit(212) == 0 and bit(203) == 1
+    before = eng.export()
+    E.stratego_step(eng.ctx, torch.tensor([212], dtype=torch.int16, device="cuda"))
+    assert eng.error() == (E.E_ILLEGAL_ACTION, 0)
+    assert torch.equal(eng.export(), before)
+    eng.close()
+
+
+@pytest.mark.parametrize("G,L", [(1, 1), (2, 4)])
+def test_fused_plies_with_both_rules(G, L):
+    recs = sparse_positions(1500, seed=11 + G)
+    n, seed = len(recs), 9
+    kw = dict(k_battleless=100, max_moves=300, auto_reset=False, two_square=True, chasing=True)
+    eng = E.Engine(n, seed, games_per_wg=G, lds_layout=L, **kw)
+    eng.load(torch.from_numpy(recs).cuda())
+    ref = O.OracleEngine.from_records(recs, seed, **kw)
+    for ply in range(120):
+        obs = ply % 40 == 0
+        E.stratego_run_plies(eng.ctx, 1, mask=eng.mask, actions=eng.actions, obs=eng.obs if obs else None,
+                             done=eng.done, outcome=eng.outcome, reason=eng.reason)
+        r = ref.ply(obs=obs)
+        assert_same(f"mask@{ply}", cpu(eng.mask), r["mask"])
+        assert_same(f"actions@{ply}", cpu(eng.actions), r["actions"])
+        if obs:
+            assert_same(f"obs@{ply}", cpu(eng.obs), r["obs"])
+        for k in ("done", "outcome", "reason"):
+            assert_same(f"{k}@{ply}", cpu(getattr(eng, k)), r[k])
+    assert_same("states", cpu(eng.export()), ref.export())
+    assert eng.error() == (0, -1)
+    eng.close()
