@@ -216,10 +216,11 @@ def rollout_buffer_bench(E, torch, n=GAMES, H=64, warm=256):
 
 
 def two_square_bench(E, torch, n=GAMES, warm=256, timed=128):
-    """The fused ply with the two-square rule on (App. A competitive play):
-    same workload as the headline run, rule enforced in masks and terminal
-    tests; also the share of games the rule restricts at the end."""
-    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True, two_square=True)
+    """The fused ply with both competitive-play rules on (App. A: two-square
+    and continuous chasing): same workload as the headline run, rules
+    enforced in masks and terminal tests; also the share of games each rule
+    restricts at the end."""
+    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True, two_square=True, chasing=True)
     obs = eng.obs
 
     def plies():
@@ -234,14 +235,15 @@ def two_square_bench(E, torch, n=GAMES, warm=256, timed=128):
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / timed
-    applies = torch.empty(n, dtype=torch.uint8, device="cuda")
-    E.stratego_history_info(eng.ctx, eng.window()[1], None, n, two_square_applies=applies)
-    share = float(applies.float().mean())
+    ts = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ch = torch.empty(n, dtype=torch.uint8, device="cuda")
+    E.stratego_history_info(eng.ctx, eng.window()[1], None, n, two_square_applies=ts, chase_applies=ch)
     assert eng.error() == (0, -1)
     eng.close()
-    out = dict(ms_per_ply=ms, game_steps_per_s=n / (ms / 1e3), restricted_share=share,
-               workload=f"{n} games, fused ply with observations, two-square rule on")
-    print(f"[bench] two-square rule: {out}", file=sys.stderr, flush=True)
+    out = dict(ms_per_ply=ms, game_steps_per_s=n / (ms / 1e3), two_square_share=float(ts.float().mean()),
+               chase_share=float(ch.float().mean()),
+               workload=f"{n} games, fused ply with observations, two-square and chasing rules on")
+    print(f"[bench] competitive rules: {out}", file=sys.stderr, flush=True)
     return out
 
 
@@ -455,7 +457,7 @@ def main():
         "plain_engine": plain,
         "serving": serving,
         "rollout_buffer": rollout_buffer,
-        "two_square_rule": two_square,
+        "competitive_rules": two_square,
         "policies": policies,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
