@@ -640,9 +640,10 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
         }
     }
 
-    /* the two-square record of the mover's side and the chase */
-    two_square_update(st, p, X, from, to);
-    chase_update(st, p, battle, from, to, A, a);
+    /* the two-square record of the mover's side and the chase, tracked only
+     * while their rules are on */
+    if (cfg->two_square) two_square_update(st, p, X, from, to);
+    if (cfg->chasing) chase_update(st, p, battle, from, to, A, a);
 
     /* 7-8. move history and counters */
     int slot = st->ply & (RING - 1);

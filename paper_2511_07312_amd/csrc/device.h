@@ -939,9 +939,10 @@ __device__ __forceinline__ void apply_action(uint8_t* R, Rules rules, int action
         }
       }
     }
-    // the two-square record of the mover's side and the chase
-    two_square_update(R, p, X, from, to);
-    chase_update(R, p, battle, from, to, A, a);
+    // the two-square record of the mover's side and the chase (tracked only
+    // while their rules are on)
+    if (rules.two_square) two_square_update(R, p, X, from, to);
+    if (rules.chasing) chase_update(R, p, battle, from, to, A, a);
     // 7-8. ring and counters
     const int slot = ply & 31;
     R[kOffRing + 2 * slot] = (uint8_t)from;

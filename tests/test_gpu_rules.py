@@ -69,7 +69,7 @@ def test_fused_plies_with_the_rule_in_sparse_positions(G, L):
     eng.close()
 
 
-def test_rule_off_keeps_the_state_but_not_the_restriction():
+def test_rule_off_matches_the_oracle():
     recs = sparse_positions(500, seed=3)
     n, seed = len(recs), 2
     eng = E.Engine(n, seed, max_moves=300, two_square=False)
