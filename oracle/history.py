@@ -82,7 +82,7 @@ class OracleRolloutBuffer:
         return OracleEngine.from_records(rec, cfg.seed, k_battleless=cfg.k_battleless,
                                          max_moves=cfg.max_moves, auto_reset=bool(cfg.auto_reset),
                                          two_square=bool(cfg.two_square), sampler=cfg.sampler,
-                                         chasing=bool(cfg.chasing))
+                                         chasing=bool(cfg.chasing), acting_obs=bool(cfg.acting_obs))
 
     def mask_at(self, t, games=None):
         return self._engine_at(t, games).mask()

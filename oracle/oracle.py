@@ -30,7 +30,8 @@ def build(force=True):
 class _Cfg(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("k_battleless", ctypes.c_int32),
                 ("max_moves", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
-                ("two_square", ctypes.c_int32), ("sampler", ctypes.c_int32), ("chasing", ctypes.c_int32)]
+                ("two_square", ctypes.c_int32), ("sampler", ctypes.c_int32), ("chasing", ctypes.c_int32),
+                ("acting_obs", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -129,13 +130,15 @@ class OracleEngine:
     """N independent games advanced by the C oracle."""
 
     def __init__(self, n, seed, k_battleless=100, max_moves=1000, auto_reset=False,
-                 game_ids=None, reset=True, two_square=False, sampler=SAMPLER_UNIFORM, chasing=False):
+                 game_ids=None, reset=True, two_square=False, sampler=SAMPLER_UNIFORM, chasing=False,
+                 acting_obs=False):
         L = lib()
         self.n = int(n)
         self.sb = int(L.orc_state_bytes())
         self.states = np.zeros(self.n * self.sb, dtype=np.uint8)
         self.cfg = _Cfg(seed, k_battleless, max_moves, 1 if auto_reset else 0, 1 if two_square else 0,
-                        int(sampler), 1 if chasing else 0)
+                        int(sampler), 1 if chasing else 0, 1 if acting_obs else 0, 0)
+        self.observers = 1 if acting_obs else 2
         if reset:
             self.reset(game_ids)
 
@@ -177,11 +180,11 @@ class OracleEngine:
 
     def encode(self, idx=None):
         if idx is None:
-            obs = np.zeros((self.n, 2, NCHAN, 10, 10), dtype=np.uint8)
+            obs = np.zeros((self.n, self.observers, NCHAN, 10, 10), dtype=np.uint8)
             lib().orc_batch_encode(_p(self.states), self.n, self._cfgp(), _p(obs))
             return obs
         ix = np.ascontiguousarray(idx, dtype=np.int32)
-        obs = np.zeros((len(ix), 2, NCHAN, 10, 10), dtype=np.uint8)
+        obs = np.zeros((len(ix), self.observers, NCHAN, 10, 10), dtype=np.uint8)
         lib().orc_batch_encode_subset(_p(self.states), _p(ix), len(ix), self._cfgp(), _p(obs))
         return obs
 
@@ -206,7 +209,8 @@ class OracleEngine:
         """New engine holding per resamples of each game (game ids base + i*per + j)."""
         out = OracleEngine(self.n * per, seed, self.cfg.k_battleless, self.cfg.max_moves,
                            bool(self.cfg.auto_reset), reset=False, two_square=bool(self.cfg.two_square),
-                           sampler=self.cfg.sampler, chasing=bool(self.cfg.chasing))
+                           sampler=self.cfg.sampler, chasing=bool(self.cfg.chasing),
+                           acting_obs=bool(self.cfg.acting_obs))
         lib().orc_batch_resample(_p(self.states), self.n, per, seed, game_id_base, _p(out.states))
         return out
 
@@ -216,7 +220,7 @@ class OracleEngine:
             mask=np.zeros((n, MASK_WORDS), dtype=np.uint64) if mask else None,
             num_legal=np.zeros(n, dtype=np.int16),
             actions=np.zeros(n, dtype=np.int16),
-            obs=np.zeros((n, 2, NCHAN, 10, 10), dtype=np.uint8) if obs else None,
+            obs=np.zeros((n, self.observers, NCHAN, 10, 10), dtype=np.uint8) if obs else None,
             done=np.zeros(n, dtype=np.int8), outcome=np.zeros(n, dtype=np.int8),
             reason=np.zeros(n, dtype=np.uint8), ep_len=np.zeros(n, dtype=np.int16))
         lib().orc_batch_ply(_p(self.states), n, self._cfgp(), _p(r["mask"]), _p(r["num_legal"]),

@@ -80,6 +80,8 @@ typedef struct {
     int32_t two_square;     /* enforce the two-square rule (App. A competitive play) */
     int32_t sampler;        /* move sampler: 0 uniform over legal actions, 1 magnet policy */
     int32_t chasing;        /* enforce the continuous-chasing rule (App. A competitive play) */
+    int32_t acting_obs;     /* encode only the acting player's information state (App. B.1) */
+    int32_t pad;
 } orc_cfg;
 
 /* rule flags passed to the move generator */
@@ -1112,20 +1114,28 @@ int orc_batch_step(orc_state* s, int n, const orc_cfg* cfg, const int16_t* actio
     return first_bad;
 }
 
+/* Both observers, or only the acting player (cfg->acting_obs: the
+ * ComputeInfostateTensor of App. B.1 is the acting player's). */
+static void encode_game(const orc_state* st, const orc_cfg* cfg, uint8_t* out) {
+    if (cfg->acting_obs) {
+        encode(st, cfg, st->ply & 1, out);
+        return;
+    }
+    for (int o = 0; o < 2; o++) encode(st, cfg, o, out + (size_t)o * NCHAN * PLANE);
+}
+
+static size_t obs_per_game(const orc_cfg* cfg) { return (size_t)(cfg->acting_obs ? 1 : 2) * NCHAN * PLANE; }
+
 void orc_batch_encode(const orc_state* s, int n, const orc_cfg* cfg, uint8_t* obs) {
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int i = 0; i < n; i++)
-        for (int o = 0; o < 2; o++)
-            encode(&s[i], cfg, o, obs + ((size_t)i * 2 + o) * NCHAN * PLANE);
+    for (int i = 0; i < n; i++) encode_game(&s[i], cfg, obs + (size_t)i * obs_per_game(cfg));
 }
 
 /* Encode only selected games (index list) into a compact output. */
 void orc_batch_encode_subset(const orc_state* s, const int32_t* idx, int m, const orc_cfg* cfg,
                              uint8_t* obs) {
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int i = 0; i < m; i++)
-        for (int o = 0; o < 2; o++)
-            encode(&s[idx[i]], cfg, o, obs + ((size_t)i * 2 + o) * NCHAN * PLANE);
+    for (int i = 0; i < m; i++) encode_game(&s[idx[i]], cfg, obs + (size_t)i * obs_per_game(cfg));
 }
 
 void orc_batch_export(const orc_state* s, int n, uint8_t* rec) {
@@ -1162,9 +1172,7 @@ void orc_batch_ply(orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int1
         if (mask) memcpy(mask + (size_t)i * MASK_WORDS, m, sizeof(m));
         if (num_legal) num_legal[i] = (int16_t)c;
         if (actions) actions[i] = (int16_t)a;
-        if (obs)
-            for (int o = 0; o < 2; o++)
-                encode(&s[i], cfg, o, obs + ((size_t)i * 2 + o) * NCHAN * PLANE);
+        if (obs) encode_game(&s[i], cfg, obs + (size_t)i * obs_per_game(cfg));
         int8_t d, oc;
         uint8_t r;
         int16_t el;

@@ -1036,3 +1036,14 @@ def test_chasing_rule_against_full_board_history():
             seen_forbidden += len(want)
     print("forbidden moves seen:", seen_forbidden)
     assert seen_forbidden >= 20, seen_forbidden
+
+
+def test_acting_player_encoding_is_the_acting_observer_of_both():
+    # App. B.1: ComputeInfostateTensor returns the acting player's information state
+    both = O.OracleEngine(40, seed=12, auto_reset=True)
+    act = O.OracleEngine(40, seed=12, auto_reset=True, acting_obs=True)
+    for ply in range(25):
+        pre = both.export()[:, 8] & 1      # acting player of the pre-move state the obs show
+        rb, ra = both.ply(obs=True), act.ply(obs=True)
+        assert ra["obs"].shape == (40, 1, 488, 10, 10)
+        assert np.array_equal(ra["obs"][:, 0], rb["obs"][np.arange(40), pre])
