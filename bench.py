@@ -84,7 +84,8 @@ def cpu_baseline(seconds=12.0):
         el = time.perf_counter() - t0
         if el >= seconds or plies >= 20000:
             break
-    return dict(value=n * plies / el, unit="game steps/s", cores=oracle.num_threads(),
+    cores = oracle.num_threads()
+    return dict(value=n * plies / el, unit="game steps/s", cores=cores, per_core=n * plies / el / cores,
                 kind="oracle",
                 sample=f"games 0..{n - 1} of the same seed, {plies} fused plies each (mask, sample, "
                        f"encode both players, step, auto-reset) after 64 unencoded plies; "
@@ -295,6 +296,41 @@ def policy_bench(E, torch, n=GAMES, warm=256, timed=128):
     return out
 
 
+def acting_player_bench(E, torch, n=GAMES, warm=256, timed=320):
+    """Secondary metric: the same fused ply writing only the acting player's
+    information state ([N, 1, 488, 10, 10], App. B.1 ComputeInfostateTensor)."""
+    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True, acting_obs=True)
+    obs = eng.obs
+    ply_ns = torch.empty(GRAPH_PLIES, dtype=torch.int64, device="cuda")
+
+    def plies(timed_run):
+        E.stratego_run_plies(eng.ctx, GRAPH_PLIES, mask=eng.mask, obs=obs, use_graph=True,
+                             ply_ns=ply_ns if timed_run else None)
+    for _ in range(warm // GRAPH_PLIES):
+        plies(False)
+    plies(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat = []
+    e0.record(stream)
+    for _ in range(timed // GRAPH_PLIES):
+        plies(True)
+        lat += [x / 1e6 for x in ply_ns.cpu().tolist()]
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / timed
+    assert eng.error() == (0, -1)
+    eng.close()
+    bytes_per_step = 48800 + 1256 + 2 + 5 + 2 * 1536
+    achieved = bytes_per_step * n / (ms / 1e3) / 1e9
+    out = dict(value=n / (ms / 1e3), unit="game steps/s", ms_per_step=ms, p50_ms=percentile(lat, 0.5),
+               p99_ms=percentile(lat, 0.99), bytes_per_game_step=bytes_per_step,
+               achieved_GBs=achieved, frac=achieved / HBM_PEAK_GBS,
+               workload=f"{n} games, fused ply, acting player's observations only")
+    print(f"[bench] acting player only: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,6 +457,8 @@ def main():
     two_square = None if args.no_history else two_square_bench(E, torch, n)
     torch.cuda.empty_cache()
     policies = None if args.no_history else policy_bench(E, torch, n)
+    torch.cuda.empty_cache()
+    acting = None if args.no_history else acting_player_bench(E, torch, n)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -455,6 +493,7 @@ def main():
             "kernel_ms_device_timestamps": kernel_ms,
         },
         "plain_engine": plain,
+        "acting_player_only": acting,
         "serving": serving,
         "rollout_buffer": rollout_buffer,
         "competitive_rules": two_square,

@@ -20,7 +20,8 @@
  *     (mask[g][a >> 6] >> (a & 63)) & 1; bits 10000..10047 are zero.
  *   - Observations are uint8 obs[N][2][488][10][10]: game, observer (0 red,
  *     1 blue), channel, row, col, in the observer's frame (blue's view is the
- *     board rotated by 180 degrees).  Indicator channels hold 1; channels
+ *     board rotated by 180 degrees); with acting_obs_only, obs[N][1][488][10][10]
+ *     holds the acting player's view only.  Indicator channels hold 1; channels
  *     12-35 and 41-42 hold round(255*x) of a probability or fraction; channels
  *     456-487 hold 0x01 at a move's destination and 0xFF (int8 -1) at its
  *     source (App. C).
@@ -84,6 +85,9 @@ typedef struct {
                               chasing player may not make a threat that recreates a position
                               of the chase (within the last 32 plies), unless the moved piece
                               returns to its square before that player's previous turn */
+  int32_t acting_obs_only; /* 1: every observation output holds only the acting player's
+                              information state, uint8[N][1][488][10][10] (App. B.1
+                              ComputeInfostateTensor); 0: both players, [N][2][488][10][10] */
 } stratego_config;
 
 /* Create a context with N games, all reset to fresh setups (episode 0).

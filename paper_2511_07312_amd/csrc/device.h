@@ -99,7 +99,13 @@ struct Rules {
   int32_t two_square;   // enforce the two-square rule
   int32_t sampler;      // 0: uniform over legal actions; 1: magnet policy
   int32_t chasing;      // enforce the continuous-chasing rule
+  int32_t acting_obs;   // encode only the acting player's information state
 };
+
+// Bytes of one game's observations: both observers, or the acting player's.
+__host__ __device__ __forceinline__ int obs_bytes_per_game(const Rules& r) {
+  return r.acting_obs ? kObsPerObserver : kObsPerGame;
+}
 enum : int { kSamplerUniform = 0, kSamplerMagnet = 1 };
 constexpr int kMaxLegal = 256;   // legal-list capacity (at most 244 legal moves exist)
 
@@ -1221,9 +1227,13 @@ __device__ __forceinline__ void encode_game_bytes(const uint8_t* R, uint8_t* sla
     SegWriter W{img, c_lo, c_hi, segb};
     scatter_segment(R, slab, rules, W);
     wave_sync();
-    stream_out(reinterpret_cast<u32x4*>(img), reinterpret_cast<u32x4*>(obs + c_lo * 100), chunks);
-    stream_out(reinterpret_cast<u32x4*>(img + segb),
-               reinterpret_cast<u32x4*>(obs + kObsPerObserver + c_lo * 100), chunks);
+    // both observers' images, or the acting player's only
+    const int first = rules.acting_obs ? (int)(hdr_u32(R, kOffPly) & 1) : 0;
+    const int count = rules.acting_obs ? 1 : 2;
+#pragma unroll 1
+    for (int k = 0; k < count; ++k)
+      stream_out(reinterpret_cast<u32x4*>(img + (first + k) * segb),
+                 reinterpret_cast<u32x4*>(obs + k * kObsPerObserver + c_lo * 100), chunks);
     wave_sync();
   }
 }
@@ -1391,8 +1401,11 @@ __device__ __forceinline__ void encode_game_bits(const uint8_t* R, uint8_t* slab
   build_bitplanes(R, slab);
   const uint32_t c41 = 0x01010101u * quant255(hdr_u32(R, kOffPly), (uint32_t)rules.max_moves);
   const uint32_t c42 = 0x01010101u * quant255(hdr_u32(R, kOffBattleless), (uint32_t)rules.k_battleless);
-  stream_bitplanes(slab, 0, c41, c42, obs);
-  stream_bitplanes(slab, 1, c41, c42, obs + kObsPerObserver);
+  // both observers, or the acting player's planes only
+  const int first = rules.acting_obs ? (int)(hdr_u32(R, kOffPly) & 1) : 0;
+  const int count = rules.acting_obs ? 1 : 2;
+#pragma unroll 1
+  for (int k = 0; k < count; ++k) stream_bitplanes(slab, first + k, c41, c42, obs + k * kObsPerObserver);
   wave_sync();
 }
 

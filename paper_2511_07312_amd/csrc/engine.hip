@@ -193,8 +193,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       if (MODE & kStepFromInput) action = a.actions_in[i];
       if (encode) {
         compute_probq(R, slab);
-        if (BITS) encode_game_bits(R, slab, a.rules, a.obs + (size_t)oi * kObsPerGame);
-        else encode_game_bytes(R, slab, a.rules, segments_of(a.layout), a.obs + (size_t)oi * kObsPerGame);
+        uint8_t* out = a.obs + (size_t)oi * obs_bytes_per_game(a.rules);
+        if (BITS) encode_game_bits(R, slab, a.rules, out);
+        else encode_game_bytes(R, slab, a.rules, segments_of(a.layout), out);
       }
       if (MODE & kDoStep) {
         if (a.hist) store_record(a.hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
@@ -415,7 +416,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
     if (h.num_legal && lane == 0) h.num_legal[i] = (int16_t)n;
   } else if (Q == kQObs) {
     compute_probq(R, slab);
-    encode_game_bits(R, slab, h.rules, h.obs + (size_t)i * kObsPerGame);
+    encode_game_bits(R, slab, h.rules, h.obs + (size_t)i * obs_bytes_per_game(h.rules));
   } else {
     const stratego_history_outputs& o = h.out;
     const int ply = (int)hdr_u32(R, kOffPly), p = ply & 1;
@@ -671,6 +672,7 @@ inline Rules rules_of(const stratego_ctx* c) {
   r.two_square = c->cfg.two_square_rule;
   r.sampler = c->cfg.sampler;
   r.chasing = c->cfg.chasing_rule;
+  r.acting_obs = c->cfg.acting_obs_only;
   return r;
 }
 
@@ -827,7 +829,8 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
       cfg->max_moves > 32767 || (cfg->auto_reset != 0 && cfg->auto_reset != 1) ||
       (cfg->two_square_rule != 0 && cfg->two_square_rule != 1) ||
       (cfg->sampler != kSamplerUniform && cfg->sampler != kSamplerMagnet) ||
-      (cfg->chasing_rule != 0 && cfg->chasing_rule != 1))
+      (cfg->chasing_rule != 0 && cfg->chasing_rule != 1) ||
+      (cfg->acting_obs_only != 0 && cfg->acting_obs_only != 1))
     return STRATEGO_E_INVAL;
   int G = cfg->games_per_wg ? cfg->games_per_wg : 1;
   int S = cfg->lds_layout ? cfg->lds_layout : kLayoutBits;
@@ -1099,8 +1102,9 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return STRATEGO_E_HIP;
     budget = (int64_t)free_b;
   }
-  auto bytes_of = [](const stratego_request& q) -> int64_t {
-    return (int64_t)q.num_games * (kRecordBytes + (q.kind == STRATEGO_REQ_STEP ? kObsPerGame : 0));
+  auto bytes_of = [&](const stratego_request& q) -> int64_t {
+    return (int64_t)q.num_games *
+           (kRecordBytes + (q.kind == STRATEGO_REQ_STEP ? obs_bytes_per_game(rules_of(c)) : 0));
   };
   for (int r = 0; r < nreq; ++r)
     if (bytes_of(reqs[r]) > budget) return STRATEGO_E_INVAL;   // could never be admitted

@@ -49,7 +49,8 @@ class StrategoConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("game_id_base", ctypes.c_uint32),
                 ("games_per_wg", ctypes.c_int32), ("lds_layout", ctypes.c_int32),
                 ("history_len", ctypes.c_int32), ("two_square_rule", ctypes.c_int32),
-                ("sampler", ctypes.c_int32), ("chasing_rule", ctypes.c_int32)]
+                ("sampler", ctypes.c_int32), ("chasing_rule", ctypes.c_int32),
+                ("acting_obs_only", ctypes.c_int32)]
 
 
 class HistoryOutputs(ctypes.Structure):
@@ -175,14 +176,16 @@ def _stream():
 # ------------------------------------------------------------------ C-ABI mirrors
 def stratego_init(num_games, seed, k_battleless=100, max_moves=4000, auto_reset=False,
                   game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, two_square=False,
-                  sampler=SAMPLER_UNIFORM, chasing=False):
+                  sampler=SAMPLER_UNIFORM, chasing=False, acting_obs=False):
     cfg = StrategoConfig(int(num_games), int(k_battleless), int(max_moves), int(bool(auto_reset)),
                          int(seed), int(game_id_base), int(games_per_wg), int(lds_layout),
-                         int(history_len), int(bool(two_square)), int(sampler), int(bool(chasing)))
+                         int(history_len), int(bool(two_square)), int(sampler), int(bool(chasing)),
+                         int(bool(acting_obs)))
     ctx = ctypes.c_void_p()
     _check(load_library().stratego_init(ctypes.byref(cfg), _stream(), ctypes.byref(ctx)),
            "stratego_init")
     _ctx_games[ctx.value] = int(num_games)
+    _ctx_obs[ctx.value] = OBS_BYTES_PER_GAME // 2 if acting_obs else OBS_BYTES_PER_GAME
     return ctx
 
 
@@ -220,7 +223,7 @@ def stratego_step(ctx, actions, done=None, outcome=None, reason=None, ep_len=Non
 def stratego_encode_obs(ctx, obs):
     n = _num_games(ctx)
     _check(load_library().stratego_encode_obs(
-        ctx, _ptr(obs, torch.uint8, n and n * OBS_BYTES_PER_GAME, "obs")), "stratego_encode_obs")
+        ctx, _ptr(obs, torch.uint8, n and n * obs_bytes_per_game(ctx), "obs")), "stratego_encode_obs")
 
 
 def stratego_export_states(ctx, states):
@@ -257,7 +260,7 @@ def stratego_history_encode_obs(ctx, t, obs, games=None, count=None):
     m = _listed(games, count)
     _check(load_library().stratego_history_encode_obs(
         ctx, int(t), _ptr(games, torch.int32, m, "games"), m,
-        _ptr(obs, torch.uint8, m * OBS_BYTES_PER_GAME, "obs")), "stratego_history_encode_obs")
+        _ptr(obs, torch.uint8, m * obs_bytes_per_game(ctx), "obs")), "stratego_history_encode_obs")
 
 
 def stratego_history_info(ctx, t, games=None, count=None, **outputs):
@@ -312,7 +315,13 @@ def _num_games(ctx):
     return _ctx_games.get(ctx.value)
 
 
+def obs_bytes_per_game(ctx):
+    """97,600 (both players) or 48,800 (acting player only)."""
+    return _ctx_obs.get(ctx.value, OBS_BYTES_PER_GAME)
+
+
 _ctx_games = {}
+_ctx_obs = {}
 
 
 def stratego_run_plies(ctx, nplies, mask=None, num_legal=None, actions=None, obs=None, done=None,
@@ -322,7 +331,7 @@ def stratego_run_plies(ctx, nplies, mask=None, num_legal=None, actions=None, obs
     _check(load_library().stratego_run_plies(
         ctx, int(nplies), _ptr(mask, torch.int64, n and n * MASK_WORDS, "mask"),
         _ptr(num_legal, torch.int16, n, "num_legal"), _ptr(actions, torch.int16, per, "actions"),
-        _ptr(obs, torch.uint8, n and n * OBS_BYTES_PER_GAME, "obs"),
+        _ptr(obs, torch.uint8, n and n * obs_bytes_per_game(ctx), "obs"),
         _ptr(done, torch.int8, per, "done"), _ptr(outcome, torch.int8, per, "outcome"),
         _ptr(reason, torch.uint8, per, "reason"), _ptr(ep_len, torch.int16, per, "ep_len"),
         int(bool(use_graph)), _ptr(ply_ns, torch.int64, int(nplies), "ply_ns")),
@@ -336,7 +345,7 @@ def stratego_run_plies_slots(ctx, slots, nplies, mask=None, actions=None, obs=No
     _check(load_library().stratego_run_plies_slots(
         ctx, _ptr(slots, torch.int32, m, "slots"), m, int(nplies),
         _ptr(mask, torch.int64, m * MASK_WORDS, "mask"), _ptr(actions, torch.int16, per, "actions"),
-        _ptr(obs, torch.uint8, m * OBS_BYTES_PER_GAME, "obs"), _ptr(done, torch.int8, per, "done"),
+        _ptr(obs, torch.uint8, m * obs_bytes_per_game(ctx), "obs"), _ptr(done, torch.int8, per, "done"),
         _ptr(outcome, torch.int8, per, "outcome"), _ptr(reason, torch.uint8, per, "reason"),
         _ptr(ep_len, torch.int16, per, "ep_len")), "stratego_run_plies_slots")
 
@@ -369,7 +378,7 @@ def stratego_serve(ctx, requests, in_states, out_states, obs_out=None, obs_by_sl
         total = max(total, int(first) + int(b))
     res = (RequestResult * max(nreq, 1))()
     st = ServeStats()
-    obs_rows = None if obs_out is None or obs_by_slot else total * OBS_BYTES_PER_GAME
+    obs_rows = None if obs_out is None or obs_by_slot else total * obs_bytes_per_game(ctx)
     _check(load_library().stratego_serve(
         ctx, reqs, nreq, _ptr(in_states, torch.uint8, total * RECORD_BYTES, "in_states"),
         _ptr(out_states, torch.uint8, total * RECORD_BYTES, "out_states"),
@@ -406,6 +415,7 @@ def stratego_current_step(ctx):
 def stratego_destroy(ctx):
     _check(load_library().stratego_destroy(ctx), "stratego_destroy")
     _ctx_games.pop(ctx.value, None)
+    _ctx_obs.pop(ctx.value, None)
 
 
 # ------------------------------------------------------------------ convenience
@@ -414,12 +424,13 @@ class Engine:
 
     def __init__(self, num_games, seed, k_battleless=100, max_moves=1000, auto_reset=False,
                  game_id_base=0, games_per_wg=0, lds_layout=0, history_len=0, two_square=False,
-                 sampler=SAMPLER_UNIFORM, chasing=False, device="cuda"):
+                 sampler=SAMPLER_UNIFORM, chasing=False, acting_obs=False, device="cuda"):
         self.n = int(num_games)
         self.device = torch.device(device)
         self.ctx = stratego_init(num_games, seed, k_battleless, max_moves, auto_reset,
                                  game_id_base, games_per_wg, lds_layout, history_len, two_square, sampler,
-                                 chasing)
+                                 chasing, acting_obs)
+        self.observers = 1 if acting_obs else 2
         n, d = self.n, self.device
         self.mask = torch.empty((n, MASK_WORDS), dtype=torch.int64, device=d)
         self.num_legal = torch.empty(n, dtype=torch.int16, device=d)
@@ -433,7 +444,7 @@ class Engine:
     @property
     def obs(self):
         if self._obs is None:
-            self._obs = torch.empty((self.n, 2, NUM_CHANNELS, 10, 10), dtype=torch.uint8,
+            self._obs = torch.empty((self.n, self.observers, NUM_CHANNELS, 10, 10), dtype=torch.uint8,
                                     device=self.device)
         return self._obs
 
@@ -507,7 +518,7 @@ class Engine:
     def obs_at(self, t, games=None, out=None):
         m = self._list(games)
         if out is None:
-            out = torch.empty((m, 2, NUM_CHANNELS, 10, 10), dtype=torch.uint8, device=self.device)
+            out = torch.empty((m, self.observers, NUM_CHANNELS, 10, 10), dtype=torch.uint8, device=self.device)
         stratego_history_encode_obs(self.ctx, t, out, games, m)
         return out
 

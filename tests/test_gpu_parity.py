@@ -403,3 +403,25 @@ def test_65536_games_graph_plies_sampled_against_oracle():
     assert_same("records", cpu(eng.export().index_select(0, idx)), ref.export())
     assert eng.error() == (0, -1)
     eng.close()
+
+
+@pytest.mark.parametrize("G,L", [(1, 1), (4, 5)])
+def test_acting_player_observations(G, L):
+    """acting_obs_only: the fused ply, the plain encoder and the rollout
+    buffer's query write only the acting player's information state (App. B.1
+    ComputeInfostateTensor), bit-exact with the oracle's."""
+    n, seed = 700, 13
+    kw = dict(k_battleless=100, max_moves=1000, auto_reset=True)
+    eng = E.Engine(n, seed, acting_obs=True, games_per_wg=G, lds_layout=L, history_len=4, **kw)
+    ref = O.OracleEngine(n, seed, acting_obs=True, **kw)
+    assert tuple(eng.obs.shape) == (n, 1, 488, 10, 10)
+    for ply in range(30):
+        E.stratego_run_plies(eng.ctx, 1, mask=eng.mask, actions=eng.actions, obs=eng.obs)
+        r = ref.ply(obs=True)
+        assert_same(f"actions@{ply}", cpu(eng.actions), r["actions"])
+        assert_same(f"obs@{ply}", cpu(eng.obs), r["obs"])
+    last = cpu(eng.obs)
+    assert_same("plain encoder", cpu(eng.encode()), ref.encode())
+    lo, T = eng.window()
+    assert_same("history obs at T-1", cpu(eng.obs_at(T - 1)), last)
+    eng.close()
