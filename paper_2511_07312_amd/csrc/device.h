@@ -1234,6 +1234,8 @@ __device__ __forceinline__ void encode_game_bytes(const uint8_t* R, uint8_t* sla
     for (int k = 0; k < count; ++k)
       stream_out(reinterpret_cast<u32x4*>(img + (first + k) * segb),
                  reinterpret_cast<u32x4*>(obs + k * kObsPerObserver + c_lo * 100), chunks);
+    // the image must be left zero: clear the other observer's, not streamed
+    if (rules.acting_obs) clear_lds(img + (1 - first) * segb, 16 * chunks);
     wave_sync();
   }
 }
