@@ -73,8 +73,9 @@ typedef struct {
   uint64_t seed;          /* Philox4x32-10 key for setups, moves and resampling */
   uint32_t game_id_base;  /* global game id of slot 0; slot i has id base + i */
   int32_t games_per_wg;   /* fused engine tile size G in {1,2,4,8,16}; 0 = default */
-  int32_t lds_layout;     /* observation staging in LDS: 1 = bit planes; 2..6 = byte images in
-                             1, 2, 4, 8, 16 channel segments; 0 = default (1) */
+  int32_t lds_layout;     /* observation staging in LDS: 1 = bit planes of both players; 2..6 =
+                             byte images in 1, 2, 4, 8, 16 channel segments; 7 = bit planes of
+                             one player at a time (half the LDS); 0 = default (1) */
   int32_t history_len;    /* rollout buffer: time steps kept (App. B.1), 0..2^20; 0 = none */
   int32_t two_square_rule; /* 1: a piece may not cross the same square boundary on more than
                               three consecutive turns of its owner (App. A, App. B.2) */

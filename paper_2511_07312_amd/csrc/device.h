@@ -55,9 +55,12 @@ constexpr int kSlabImage = 1792;    // obs image segment (also holds the to-squa
 // Observation staging layouts in LDS (the autotuner's "LDS layout" knob):
 //   kLayoutBits (1): bit planes, one bit per output byte, both observers
 //     staged at once (6.1 KB each) and expanded to bytes while streaming out;
-//   2..6: byte images of both observers in 1, 2, 4, 8, 16 channel segments.
+//   2..6: byte images of both observers in 1, 2, 4, 8, 16 channel segments;
+//   kLayoutBits1 (7): bit planes of one observer at a time (half the LDS of
+//     layout 1, so twice the waves per CU, for a second pass over the pieces).
 constexpr int kLayoutBits = 1;
-__host__ __device__ __forceinline__ constexpr bool valid_layout(int L) { return L >= 1 && L <= 6; }
+constexpr int kLayoutBits1 = 7;
+__host__ __device__ __forceinline__ constexpr bool valid_layout(int L) { return L >= 1 && L <= 7; }
 __host__ __device__ __forceinline__ constexpr int segments_of(int L) { return L <= 1 ? 1 : 1 << (L - 2); }
 
 // Channels per image segment (multiples of 4, so segments stay 16-byte aligned).
@@ -79,13 +82,21 @@ constexpr int kBitsCat0 = kBitsMove1 + kBitsMovePlane;    // uint8 [100] per obs
 constexpr int kBitsCat1 = kBitsCat0 + 112;
 constexpr int kBitsTab = kBitsCat1 + 112;                 // uint64 [2][24]
 constexpr int kBitsSlabBytes = kBitsTab + 2 * 24 * 8;
+// one-observer bit-plane layout
+constexpr int kB1Plane = kSlabImage;
+constexpr int kB1Move = kB1Plane + kBitsPlane;
+constexpr int kB1Cat = kB1Move + kBitsMovePlane;          // uint8 [100]
+constexpr int kB1Tab = kB1Cat + 112;                      // uint64 [24]
+constexpr int kB1SlabBytes = kB1Tab + 24 * 8;
 
 __host__ __device__ __forceinline__ constexpr int slab_bytes_for(int L) {
-  return L == kLayoutBits ? kBitsSlabBytes : kSlabImage + 2 * seg_bytes_for(segments_of(L));
+  return L == kLayoutBits ? kBitsSlabBytes : L == kLayoutBits1 ? kB1SlabBytes
+                                           : kSlabImage + 2 * seg_bytes_for(segments_of(L));
 }
 // LDS bytes that must be zero when a game's encoding starts
 __host__ __device__ __forceinline__ constexpr int image_bytes_for(int L) {
-  return L == kLayoutBits ? kBitsCat0 - kSlabImage : 2 * seg_bytes_for(segments_of(L));
+  return L == kLayoutBits ? kBitsCat0 - kSlabImage : L == kLayoutBits1 ? kB1Cat - kSlabImage
+                                                   : 2 * seg_bytes_for(segments_of(L));
 }
 
 enum : int { kReasonNone = 0, kReasonFlag = 1, kReasonForcedWin = 2, kReasonForcedDraw = 3,
@@ -1357,12 +1368,8 @@ __device__ __forceinline__ void build_bitplanes(const uint8_t* R, uint8_t* slab)
 // Expand observer o's bit planes to 48800 bytes in global memory: each lane
 // turns 16 plane bits into one 16-byte chunk; consecutive lanes write
 // consecutive chunks (1 KB per wave store).
-__device__ __forceinline__ void stream_bitplanes(const uint8_t* slab, int o, uint32_t c41, uint32_t c42,
-                                                 uint8_t* out) {
-  const uint16_t* bm = reinterpret_cast<const uint16_t*>(slab + (o ? kBitsPlane1 : kBitsPlane0));
-  const uint16_t* mv = reinterpret_cast<const uint16_t*>(slab + (o ? kBitsMove1 : kBitsMove0));
-  const uint8_t* cat = slab + (o ? kBitsCat1 : kBitsCat0);
-  const uint64_t* tab = reinterpret_cast<const uint64_t*>(slab + kBitsTab) + 24 * o;
+__device__ __forceinline__ void stream_planes(const uint16_t* bm, const uint16_t* mv, const uint8_t* cat,
+                                              const uint64_t* tab, uint32_t c41, uint32_t c42, uint8_t* out) {
   u32x4* dst = reinterpret_cast<u32x4*>(out);
   constexpr int kChunks = kObsPerObserver / 16;   // 3050
 #pragma unroll 2
@@ -1398,6 +1405,122 @@ __device__ __forceinline__ void stream_bitplanes(const uint8_t* slab, int o, uin
   }
 }
 
+__device__ __forceinline__ void stream_bitplanes(const uint8_t* slab, int o, uint32_t c41, uint32_t c42,
+                                                 uint8_t* out) {
+  stream_planes(reinterpret_cast<const uint16_t*>(slab + (o ? kBitsPlane1 : kBitsPlane0)),
+                reinterpret_cast<const uint16_t*>(slab + (o ? kBitsMove1 : kBitsMove0)),
+                slab + (o ? kBitsCat1 : kBitsCat0), reinterpret_cast<const uint64_t*>(slab + kBitsTab) + 24 * o,
+                c41, c42, out);
+}
+
+// Observer o's planes only (layout kLayoutBits1): the same channels as
+// build_bitplanes, each piece seen from o's side, in o's frame.
+__device__ __forceinline__ void build_bitplanes1(const uint8_t* R, uint8_t* slab, int o) {
+  const int lane = lane_id();
+  const int ply = (int)hdr_u32(R, kOffPly);
+  uint32_t* bm = reinterpret_cast<uint32_t*>(slab + kB1Plane);
+  auto set = [&](int c, int f) {
+    const int bit = 100 * c + f;
+    atomicOr(&bm[bit >> 5], 1u << (bit & 31));
+  };
+  auto fr = [&](int sq) { return o == 0 ? sq : 99 - sq; };
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int s = lane + 64 * h;
+    if (s >= kSquares) break;
+    const int id = board_at(R, s), f = fr(s);
+    uint8_t cat = 0;
+    if (id == kEmpty) {
+      set(38, f);
+    } else if (id >= 0) {
+      const bool own = owner(id) == o;
+      const uint32_t* pw = piece_words(R, id);
+      const uint32_t w0 = pw[0];
+      const int t = p_type(w0);
+      const bool rev = p_revealed(w0), mv = p_moved(w0);
+      if (own) set(t, f);
+      if (rev) set((own ? 24 : 12) + t, f);
+      else {
+        set(own ? 36 : 37, f);
+        cat = own ? (mv ? 3 : 4) : (mv ? 1 : 2);
+      }
+      if (mv) set(own ? 39 : 40, f);
+      uint32_t th = pw[1] & 0x7FFu, ev = (pw[1] >> 11) & 0x7FFu, ad = pw[2] & 0x7FFu;
+      const int b_th = own ? 43 : 76, b_ev = own ? 54 : 87, b_ad = own ? 65 : 98;
+      while (th) { int j = __ffs(th) - 1; th &= th - 1; set(b_th + j, f); }
+      while (ev) { int j = __ffs(ev) - 1; ev &= ev - 1; set(b_ev + j, f); }
+      while (ad) { int j = __ffs(ad) - 1; ad &= ad - 1; set(b_ad + j, f); }
+      uint32_t pr = (pw[2] >> 11) & 0x1FFFu, pa = pw[3] & 0x1FFFu;
+      uint32_t bb = (pw[3] >> 13) & 0x1FFFu, ba = (w0 >> 17) & 0x1FFFu;
+      const int b_pr = own ? 251 : 303, b_pa = own ? 264 : 316, b_bb = own ? 277 : 329, b_ba = own ? 290 : 342;
+      while (pr) { int j = __ffs(pr) - 1; pr &= pr - 1; set(b_pr + j, f); }
+      while (pa) { int j = __ffs(pa) - 1; pa &= pa - 1; set(b_pa + j, f); }
+      while (bb) { int j = __ffs(bb) - 1; bb &= bb - 1; set(b_bb + j, f); }
+      while (ba) { int j = __ffs(ba) - 1; ba &= ba - 1; set(b_ba + j, f); }
+      set(355 + fr(start_sq(id)), f);
+    }
+    slab[kB1Cat + f] = cat;
+  }
+  // captured pieces: start squares (109-130) and death square x cause (131-250)
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int id = lane + 64 * h;
+    if (id >= kPieces) break;
+    const uint32_t w0 = piece_words(R, id)[0];
+    if (p_alive(w0)) continue;
+    const int t = p_type(w0);
+    if (t == kFlag) continue;
+    const bool own = owner(id) == o;
+    const int slot = t == kBomb ? 10 : t;
+    set((own ? 109 : 120) + slot, fr(start_sq(id)));
+    if (t <= kMarshal) {
+      const int cause = (w0 >> 7) & 7, dsq = (w0 >> 10) & 127;
+      set((own ? 131 : 191) + 10 * (cause - 1) + t, fr(dsq));
+    }
+  }
+  // recent moves (456-487): destinations in the plane, sources in the side plane
+  const int rc = R[kOffRingCount];
+  if (lane < rc) {
+    const int slot = (ply - 1 - lane) & 31;
+    const int from = R[kOffRing + 2 * slot], to = R[kOffRing + 2 * slot + 1];
+    set(456 + lane, fr(to));
+    uint32_t* m = reinterpret_cast<uint32_t*>(slab + kB1Move);
+    const int b = 100 * lane + fr(from);
+    atomicOr(&m[b >> 5], 1u << (b & 31));
+  }
+  // probability table of observer o, indexed by category
+  if (lane < 24) {
+    const int j = lane;
+    const uint8_t* pq = slab + kSlabProbQ;
+    uint64_t tab;
+    if (j < 12) {   // channel 12 + j: the opponent's pieces, type j
+      const int z = 1 - o;
+      tab = ((uint64_t)pq[24 * z + 12 + j] << 8) | ((uint64_t)pq[24 * z + j] << 16);
+    } else {        // channel 24 + (j - 12): own pieces, type j - 12
+      tab = ((uint64_t)pq[24 * o + 12 + (j - 12)] << 24) | ((uint64_t)pq[24 * o + (j - 12)] << 32);
+    }
+    reinterpret_cast<uint64_t*>(slab + kB1Tab)[j] = tab;
+  }
+  wave_sync();
+}
+
+// Layout kLayoutBits1: build, stream and clear one observer's planes at a time.
+__device__ __forceinline__ void encode_game_bits1(const uint8_t* R, uint8_t* slab, Rules rules, uint8_t* obs) {
+  const uint32_t c41 = 0x01010101u * quant255(hdr_u32(R, kOffPly), (uint32_t)rules.max_moves);
+  const uint32_t c42 = 0x01010101u * quant255(hdr_u32(R, kOffBattleless), (uint32_t)rules.k_battleless);
+  const int first = rules.acting_obs ? (int)(hdr_u32(R, kOffPly) & 1) : 0;
+  const int count = rules.acting_obs ? 1 : 2;
+#pragma unroll 1
+  for (int k = 0; k < count; ++k) {
+    clear_lds(slab + kSlabImage, image_bytes_for(kLayoutBits1));
+    build_bitplanes1(R, slab, first + k);
+    stream_planes(reinterpret_cast<const uint16_t*>(slab + kB1Plane),
+                  reinterpret_cast<const uint16_t*>(slab + kB1Move), slab + kB1Cat,
+                  reinterpret_cast<const uint64_t*>(slab + kB1Tab), c41, c42, obs + k * kObsPerObserver);
+    wave_sync();
+  }
+}
+
 __device__ __forceinline__ void encode_game_bits(const uint8_t* R, uint8_t* slab, Rules rules, uint8_t* obs) {
   clear_lds(slab + kSlabImage, image_bytes_for(kLayoutBits));
   build_bitplanes(R, slab);
@@ -1417,6 +1540,7 @@ __device__ __forceinline__ void encode_game_bits(const uint8_t* R, uint8_t* slab
 __device__ __forceinline__ void encode_game(const uint8_t* R, uint8_t* slab, Rules rules, int layout,
                             uint8_t* obs) {
   if (layout == kLayoutBits) encode_game_bits(R, slab, rules, obs);
+  else if (layout == kLayoutBits1) encode_game_bits1(R, slab, rules, obs);
   else encode_game_bytes(R, slab, rules, segments_of(layout), obs);
 }
 

@@ -73,7 +73,9 @@ __device__ __forceinline__ uint64_t pack_step(int action, const StepOut& o) {
 // counter tracks both, and waiting for a load would also drain the stores).
 __host__ __device__ __forceinline__ constexpr int wave_lds_bytes(int layout) { return slab_bytes_for(layout) + kRecordBytes; }
 
-template <int MODE, bool BITS>
+// ENC: 0 byte images (layouts 2-6), 1 bit planes of both observers (layout 1),
+// 2 bit planes of one observer at a time (layout 7).
+template <int MODE, int ENC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ply(PlyArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
@@ -84,7 +86,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   if (a.ts && threadIdx.x == 0) atomicMin(&a.ts[0], (unsigned long long)wall_clock64());
   const bool encode = (MODE & kDoEncode) && a.obs;
   const size_t hist_row = ((MODE & kDoStep) && a.hist) ? (size_t)(*a.hist_slot) * (size_t)a.total : 0;
-  const bool byte_image = encode && a.layout != kLayoutBits;
+  const bool byte_image = encode && ENC == 0;
   if (byte_image) clear_lds(slab + kSlabImage, image_bytes_for(a.layout));
   const int G = a.games_per_tile;
   const int ntiles = (a.n + G - 1) / G;
@@ -194,7 +196,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       if (encode) {
         compute_probq(R, slab);
         uint8_t* out = a.obs + (size_t)oi * obs_bytes_per_game(a.rules);
-        if (BITS) encode_game_bits(R, slab, a.rules, out);
+        if (ENC == 1) encode_game_bits(R, slab, a.rules, out);
+        else if (ENC == 2) encode_game_bits1(R, slab, a.rules, out);
         else encode_game_bytes(R, slab, a.rules, segments_of(a.layout), out);
       }
       if (MODE & kDoStep) {
@@ -695,6 +698,12 @@ inline int waves_for(int G, int S) {
 // Dynamic LDS of one fused-engine workgroup.
 inline size_t lds_for(int G, int S) { return (size_t)waves_for(G, S) * wave_lds_bytes(S); }
 
+const void* fused_kernel(int enc) {
+  return enc == 1 ? reinterpret_cast<const void*>(&k_ply<kFused, 1>)
+       : enc == 2 ? reinterpret_cast<const void*>(&k_ply<kFused, 2>)
+                  : reinterpret_cast<const void*>(&k_ply<kFused, 0>);
+}
+
 // grow: observation-free plies, where a game is short next to a ticket round
 // trip; the tile grows up to 8 games while every wave still gets two or more.
 int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent,
@@ -702,20 +711,20 @@ int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S
   const int W = (mode == kFused) ? waves_for(G, S) : 4;
   const size_t lds = (size_t)W * wave_lds_bytes(S);
   if (lds > c->max_lds) return STRATEGO_E_INVAL;
-  const bool bits = S == kLayoutBits;
+  const int enc = S == kLayoutBits ? 1 : S == kLayoutBits1 ? 2 : 0;
   const void* fn = nullptr;
   switch (mode) {
     case kFused:
-      fn = bits ? reinterpret_cast<const void*>(&k_ply<kFused, true>)
-                : reinterpret_cast<const void*>(&k_ply<kFused, false>);
+      fn = fused_kernel(enc);
       break;
-    case kDoMask: fn = reinterpret_cast<const void*>(&k_ply<kDoMask, false>); break;
+    case kDoMask: fn = reinterpret_cast<const void*>(&k_ply<kDoMask, 0>); break;
     case kDoEncode:
-      fn = bits ? reinterpret_cast<const void*>(&k_ply<kDoEncode, true>)
-                : reinterpret_cast<const void*>(&k_ply<kDoEncode, false>);
+      fn = enc == 1 ? reinterpret_cast<const void*>(&k_ply<kDoEncode, 1>)
+         : enc == 2 ? reinterpret_cast<const void*>(&k_ply<kDoEncode, 2>)
+                    : reinterpret_cast<const void*>(&k_ply<kDoEncode, 0>);
       break;
     case kDoStep | kStepFromInput:
-      fn = reinterpret_cast<const void*>(&k_ply<kDoStep | kStepFromInput, false>);
+      fn = reinterpret_cast<const void*>(&k_ply<kDoStep | kStepFromInput, 0>);
       break;
     default: return STRATEGO_E_INVAL;
   }
@@ -906,10 +915,10 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int32_t*>(c->hist_clock), 2, 0);
   }
   // kernels whose dynamic LDS may exceed the default limit
-  const void* big_lds[] = {reinterpret_cast<const void*>(&k_ply<kFused, true>),
-                           reinterpret_cast<const void*>(&k_ply<kFused, false>),
-                           reinterpret_cast<const void*>(&k_ply<kDoEncode, true>),
-                           reinterpret_cast<const void*>(&k_ply<kDoEncode, false>)};
+  const void* big_lds[] = {fused_kernel(0), fused_kernel(1), fused_kernel(2),
+                           reinterpret_cast<const void*>(&k_ply<kDoEncode, 0>),
+                           reinterpret_cast<const void*>(&k_ply<kDoEncode, 1>),
+                           reinterpret_cast<const void*>(&k_ply<kDoEncode, 2>)};
   for (const void* f : big_lds)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->max_lds);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, c->err, 2, INT_MAX);
@@ -1291,17 +1300,16 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   const int Gs[5] = {1, 2, 4, 8, 16};
-  const int Ss[6] = {1, 2, 3, 4, 5, 6};
+  const int Ss[7] = {1, 2, 3, 4, 5, 6, 7};
   int best_G = c->G, best_S = c->S, count = 0;
   float best = 1e30f;
   int rc = STRATEGO_OK;
   for (int gi = 0; gi < 5 && rc == STRATEGO_OK; ++gi) {
-    for (int si = 0; si < 6 && rc == STRATEGO_OK; ++si) {
+    for (int si = 0; si < 7 && rc == STRATEGO_OK; ++si) {
       const int G = Gs[gi], S = Ss[si];
       if (lds_for(G, S) > c->max_lds) continue;
       int per_cu = 0;
-      const void* fused = S == kLayoutBits ? reinterpret_cast<const void*>(&k_ply<kFused, true>)
-                                           : reinterpret_cast<const void*>(&k_ply<kFused, false>);
+      const void* fused = fused_kernel(S == kLayoutBits ? 1 : S == kLayoutBits1 ? 2 : 0);
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64 * waves_for(G, S), lds_for(G, S)) !=
               hipSuccess ||
           per_cu <= 0)
@@ -1334,7 +1342,7 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
   if (rc != STRATEGO_OK) return rc;
   c->G = best_G;
   c->S = best_S;
-  if (n_entries) *n_entries = count;
+  if (n_entries) *n_entries = report ? (count < max_entries ? count : max_entries) : 0;   // rows written
   return STRATEGO_OK;
 }
 

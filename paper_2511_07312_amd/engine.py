@@ -357,7 +357,7 @@ def stratego_reset_resampled(ctx, src_states, per, game_id_base=0):
         int(game_id_base)), "stratego_reset_resampled")
 
 
-def stratego_autotune(ctx, obs, mask, plies=3, max_entries=32):
+def stratego_autotune(ctx, obs, mask, plies=3, max_entries=64):
     rep = (TuneEntry * max_entries)()
     n = ctypes.c_int32()
     _check(load_library().stratego_autotune(ctx, _ptr(obs, torch.uint8, None, "obs"),

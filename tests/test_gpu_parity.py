@@ -56,8 +56,8 @@ def test_plain_engine_256_games_200_plies():
 
 # ---------------------------------------------------------------- fused engine
 # (games per workgroup, LDS layout): layout 1 = bit planes, 2..6 = byte images
-# in 1, 2, 4, 8, 16 channel segments
-TILINGS = [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (1, 2), (2, 3), (4, 4), (8, 5), (16, 6)]
+# in 1, 2, 4, 8, 16 channel segments, 7 = bit planes of one observer at a time
+TILINGS = [(1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (1, 2), (2, 3), (4, 4), (8, 5), (16, 6), (1, 7), (4, 7)]
 
 
 @pytest.mark.parametrize("G,L", TILINGS)
@@ -405,7 +405,7 @@ def test_65536_games_graph_plies_sampled_against_oracle():
     eng.close()
 
 
-@pytest.mark.parametrize("G,L", [(1, 1), (4, 5)])
+@pytest.mark.parametrize("G,L", [(1, 1), (4, 5), (2, 7)])
 def test_acting_player_observations(G, L):
     """acting_obs_only: the fused ply, the plain encoder and the rollout
     buffer's query write only the acting player's information state (App. B.1
