@@ -308,6 +308,8 @@ def acting_player_bench(E, torch, n=GAMES, warm=256, timed=320):
                              ply_ns=ply_ns if timed_run else None)
     for _ in range(warm // GRAPH_PLIES):
         plies(False)
+    tune = E.stratego_autotune(eng.ctx, obs, eng.mask, plies=4)
+    G, S = E.stratego_get_tiling(eng.ctx)
     plies(True)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -325,7 +327,8 @@ def acting_player_bench(E, torch, n=GAMES, warm=256, timed=320):
     achieved = bytes_per_step * n / (ms / 1e3) / 1e9
     out = dict(value=n / (ms / 1e3), unit="game steps/s", ms_per_step=ms, p50_ms=percentile(lat, 0.5),
                p99_ms=percentile(lat, 0.99), bytes_per_game_step=bytes_per_step,
-               achieved_GBs=achieved, frac=achieved / HBM_PEAK_GBS,
+               achieved_GBs=achieved, frac=achieved / HBM_PEAK_GBS, games_per_wg=G, lds_layout=S,
+               autotune=[dict(games_per_wg=g, lds_layout=s_, us_per_ply=u) for g, s_, u in tune],
                workload=f"{n} games, fused ply, acting player's observations only")
     print(f"[bench] acting player only: {out}", file=sys.stderr, flush=True)
     return out
