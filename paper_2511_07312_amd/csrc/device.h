@@ -1368,8 +1368,14 @@ __device__ __forceinline__ void build_bitplanes(const uint8_t* R, uint8_t* slab)
 // Expand observer o's bit planes to 48800 bytes in global memory: each lane
 // turns 16 plane bits into one 16-byte chunk; consecutive lanes write
 // consecutive chunks (1 KB per wave store).
-__device__ __forceinline__ void stream_planes(const uint16_t* bm, const uint16_t* mv, const uint8_t* cat,
-                                              const uint64_t* tab, uint32_t c41, uint32_t c42, uint8_t* out) {
+template <int L>
+__device__ __forceinline__ void stream_planes(const uint8_t* slab, int o, uint32_t c41, uint32_t c42, uint8_t* out) {
+  // layout 1 keeps both observers' planes side by side; layout 7 one set
+  const uint16_t* bm = reinterpret_cast<const uint16_t*>(slab + (L == kLayoutBits ? kBitsPlane0 + o * kBitsPlane : kB1Plane));
+  const uint16_t* mv =
+      reinterpret_cast<const uint16_t*>(slab + (L == kLayoutBits ? kBitsMove0 + o * kBitsMovePlane : kB1Move));
+  const uint8_t* cat = slab + (L == kLayoutBits ? kBitsCat0 + o * 112 : kB1Cat);
+  const uint64_t* tab = reinterpret_cast<const uint64_t*>(slab + (L == kLayoutBits ? kBitsTab + o * 192 : kB1Tab));
   u32x4* dst = reinterpret_cast<u32x4*>(out);
   constexpr int kChunks = kObsPerObserver / 16;   // 3050
 #pragma unroll 2
@@ -1407,10 +1413,7 @@ __device__ __forceinline__ void stream_planes(const uint16_t* bm, const uint16_t
 
 __device__ __forceinline__ void stream_bitplanes(const uint8_t* slab, int o, uint32_t c41, uint32_t c42,
                                                  uint8_t* out) {
-  stream_planes(reinterpret_cast<const uint16_t*>(slab + (o ? kBitsPlane1 : kBitsPlane0)),
-                reinterpret_cast<const uint16_t*>(slab + (o ? kBitsMove1 : kBitsMove0)),
-                slab + (o ? kBitsCat1 : kBitsCat0), reinterpret_cast<const uint64_t*>(slab + kBitsTab) + 24 * o,
-                c41, c42, out);
+  stream_planes<kLayoutBits>(slab, o, c41, c42, out);
 }
 
 // Observer o's planes only (layout kLayoutBits1): the same channels as
@@ -1514,9 +1517,7 @@ __device__ __forceinline__ void encode_game_bits1(const uint8_t* R, uint8_t* sla
   for (int k = 0; k < count; ++k) {
     clear_lds(slab + kSlabImage, image_bytes_for(kLayoutBits1));
     build_bitplanes1(R, slab, first + k);
-    stream_planes(reinterpret_cast<const uint16_t*>(slab + kB1Plane),
-                  reinterpret_cast<const uint16_t*>(slab + kB1Move), slab + kB1Cat,
-                  reinterpret_cast<const uint64_t*>(slab + kB1Tab), c41, c42, obs + k * kObsPerObserver);
+    stream_planes<kLayoutBits1>(slab, 0, c41, c42, obs + k * kObsPerObserver);
     wave_sync();
   }
 }

@@ -76,7 +76,7 @@ __host__ __device__ __forceinline__ constexpr int wave_lds_bytes(int layout) { r
 // ENC: 0 byte images (layouts 2-6), 1 bit planes of both observers (layout 1),
 // 2 bit planes of one observer at a time (layout 7).
 template <int MODE, int ENC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ply(PlyArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : 4))) k_ply(PlyArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
   uint8_t* slab = smem + wave * wave_lds_bytes(a.layout);
