@@ -831,7 +831,17 @@ const char* stratego_strerror(int code) {
   }
 }
 
+static int init_context(const stratego_config* cfg, void* hip_stream, stratego_ctx** out);
+
 int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** out) {
+  const int rc = init_context(cfg, hip_stream, out);
+  // a failed allocation leaves its error pending in the runtime; clear it so
+  // that later calls do not report it as their own
+  if (rc == STRATEGO_E_NOMEM) (void)hipGetLastError();
+  return rc;
+}
+
+static int init_context(const stratego_config* cfg, void* hip_stream, stratego_ctx** out) {
   if (!cfg || !out) return STRATEGO_E_INVAL;
   *out = nullptr;
   if (cfg->num_games <= 0 || cfg->k_battleless <= 0 || cfg->max_moves <= 0 ||
