@@ -549,7 +549,8 @@ __global__ void __launch_bounds__(256) k_policy(PolicyArgs a) {
   load_record(R, a.states + (size_t)i * kRecordBytes);
   const uint64_t* ts = reinterpret_cast<const uint64_t*>(slab + kSlabImage);
   uint64_t w[3];
-  const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
+  const int n_all = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
+  const int n = n_all < kMaxLegal ? n_all : kMaxLegal;
   // the legal list, ascending: word order, then bit order
   int16_t* list = reinterpret_cast<int16_t*>(slab + kPolicyList);
   int base = 0;
@@ -560,8 +561,9 @@ __global__ void __launch_bounds__(256) k_policy(PolicyArgs a) {
     const int c = __popcll(v);
     const int incl = wave_incl_scan(c);
     int pos = base + incl - c;
-    while (v) {
-      list[pos++] = (int16_t)(64 * word + __ffsll((unsigned long long)v) - 1);
+    while (v) {   // at most 244 legal moves exist; the bound only guards the buffer
+      if (pos < kMaxLegal) list[pos] = (int16_t)(64 * word + __ffsll((unsigned long long)v) - 1);
+      ++pos;
       v &= v - 1;
     }
     base += __shfl(incl, 63, 64);
