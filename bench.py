@@ -10,7 +10,9 @@ synthetic: uniform random setups from the seed and uniform random legal play.
 Prints one JSON line.  Also reports per-ply p50/p99 latency (device
 timestamps), the HBM roofline fraction of the fused ply kernel, the plain
 per-call engine at the same size, serving under load, the rollout buffer
-(recording plies and queries at past steps), the autotuner table and the CPU
+(recording plies and queries at past steps), the competitive-play rules, the
+policy kernels, the acting-player-only variant, the search-shaped load
+(resampling and rollouts at 262,144 games), the autotuner table and the CPU
 oracle timed on a bounded sample of the same workload.
 """
 import argparse
@@ -334,6 +336,57 @@ def acting_player_bench(E, torch, n=GAMES, warm=256, timed=320):
     return out
 
 
+def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
+    """The search-shaped load (section 2.5 / App. B): 1024 mid-game states
+    from random play to ply 100, 256 resamples of the opponent's hidden
+    pieces each (262,144 games materialised on the device), then 50 random
+    plies of every resampled game with their per-ply outcomes."""
+    pool = 4096
+    src_eng = E.Engine(pool, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=False)
+    E.stratego_run_plies(src_eng.ctx, 100, use_graph=True)
+    recs = src_eng.export()
+    live = torch.nonzero(recs[:, 17] == 0).flatten()[:n_src]
+    assert live.numel() == n_src, live.numel()
+    src = recs[live].contiguous()
+    src_eng.close()
+    n = n_src * per
+    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=False)
+    done = torch.empty((plies, n), dtype=torch.int8, device="cuda")
+    outc = torch.empty((plies, n), dtype=torch.int8, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def load():
+        E.stratego_reset_resampled(eng.ctx, src, per, 0)
+        E.stratego_run_plies(eng.ctx, plies, done=done, outcome=outc, use_graph=True)
+    load()                                   # captures the rollout graph
+    res_ms, roll_ms = [], []
+    for _ in range(reps):
+        ev[0].record(stream)
+        E.stratego_reset_resampled(eng.ctx, src, per, 0)
+        ev[1].record(stream)
+        E.stratego_run_plies(eng.ctx, plies, done=done, outcome=outc, use_graph=True)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        res_ms.append(ev[0].elapsed_time(ev[1]))
+        roll_ms.append(ev[1].elapsed_time(ev[2]))
+    ended = float((done[-1] != 0).float().mean())
+    assert eng.error() == (0, -1)
+    eng.close()
+    r, w = min(res_ms), min(roll_ms)
+    # resample: each new record (1536 B) written, its source read once per
+    # game from cache; rollout ply: record read + written, done + outcome
+    res_bytes = n * 1536 + n_src * 1536
+    out = dict(games=n, resample_ms=r, resample_GBs=res_bytes / (r / 1e3) / 1e9,
+               rollout_ms=w, rollout_ms_per_ply=w / plies,
+               rollout_game_steps_per_s=n * plies / (w / 1e3), total_ms=r + w,
+               resampled_states_per_s=n / (r / 1e3), ended_within_50_plies=ended,
+               workload=f"{n_src} ply-100 states x {per} resamples, {plies} random plies each "
+                        "(no observations), best of {reps} runs".replace("{reps}", str(reps)))
+    print(f"[bench] search-shaped load: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,7 +398,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-extras", "--no-history", dest="no_history", action="store_true",
-                    help="skip the rollout-buffer, two-square and policy legs")
+                    help="skip the rollout-buffer, rules, policy, acting-player and search legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--tiling", default=None,
@@ -462,6 +515,8 @@ def main():
     policies = None if args.no_history else policy_bench(E, torch, n)
     torch.cuda.empty_cache()
     acting = None if args.no_history else acting_player_bench(E, torch, n)
+    torch.cuda.empty_cache()
+    search = None if args.no_history else search_bench(E, torch)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -492,7 +547,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "HBM bytes per ply launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "algorithmic_bytes_per_launch": BYTES_PER_GAME_STEP * n,
-            "kernel": "k_ply<15> (fused ply)", "bytes_per_game_step": BYTES_PER_GAME_STEP,
+            "kernel": f"k_ply<15, {1 if S == 1 else 2 if S == 7 else 0}> (fused ply)",
+            "bytes_per_game_step": BYTES_PER_GAME_STEP,
             "kernel_ms_device_timestamps": kernel_ms,
         },
         "plain_engine": plain,
@@ -501,6 +557,7 @@ def main():
         "rollout_buffer": rollout_buffer,
         "competitive_rules": two_square,
         "policies": policies,
+        "search_shaped": search,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }
