@@ -390,7 +390,7 @@ def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=640, help="timed plies (multiple of 64)")
+    ap.add_argument("--steps", type=int, default=6400, help="timed plies (multiple of 64)")
     ap.add_argument("--warmup", type=int, default=1024, help="untimed plies before timing")
     ap.add_argument("--games", type=int, default=GAMES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -483,6 +483,22 @@ def main():
     print(f"[bench] timed {steps} plies: {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms)",
           file=sys.stderr, flush=True)
 
+    # store-only ceiling: PyTorch's fill of the same observation tensor (one
+    # 16-byte store per thread, in address order)
+    fill_ms = []
+    for _ in range(6):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        obs.fill_(1)
+        e1.record(stream)
+        e1.synchronize()
+        fill_ms.append(e0.elapsed_time(e1))
+    fill_gbs = obs.numel() / (min(fill_ms[1:]) / 1e3) / 1e9
+    store_ceiling = dict(kernel="torch fill_ of the observation tensor", GBs=fill_gbs,
+                         fused_ply_frac=achieved / fill_gbs)
+    print(f"[bench] store ceiling: {store_ceiling}", file=sys.stderr, flush=True)
+
     plain = None
     if not args.no_plain:
         pl = []
@@ -551,6 +567,7 @@ def main():
             "bytes_per_game_step": BYTES_PER_GAME_STEP,
             "kernel_ms_device_timestamps": kernel_ms,
         },
+        "store_ceiling": store_ceiling,
         "plain_engine": plain,
         "acting_player_only": acting,
         "serving": serving,

@@ -147,35 +147,38 @@ def test_game_id_offset_shards_match_single_context():
 # ---------------------------------------------------------------- play to the end
 def test_4096_games_to_terminal_histograms():
     """4096 games of random play without auto-reset until every game ends (or the
-    1000-ply cap): outcome/reason and game-length histograms equal the oracle's,
-    and so do the final states and sampled observations."""
-    n, seed, chunk = 4096, 2, 50
+    1000-ply cap), one fused ply per launch: every ply's actions and done flags,
+    the observations of 64 games (a different 64 each ply) and of all games at
+    a few plies equal the oracle's, as do the final states and the
+    outcome/reason and game-length histograms."""
+    n, seed, sub = 4096, 2, 64
     eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=False)
     ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=False)
-    acts = torch.empty((chunk, n), dtype=torch.int16, device="cuda")
-    done = torch.empty((chunk, n), dtype=torch.int8, device="cuda")
-    outc = torch.empty((chunk, n), dtype=torch.int8, device="cuda")
-    reas = torch.empty((chunk, n), dtype=torch.uint8, device="cuda")
-    epl = torch.empty((chunk, n), dtype=torch.int16, device="cuda")
+    acts = torch.empty((1, n), dtype=torch.int16, device="cuda")
+    done = torch.empty((1, n), dtype=torch.int8, device="cuda")
+    outc = torch.empty((1, n), dtype=torch.int8, device="cuda")
+    reas = torch.empty((1, n), dtype=torch.uint8, device="cuda")
+    epl = torch.empty((1, n), dtype=torch.int16, device="cuda")
+    full_obs_at = {0, 1, 2, 49, 99, 149, 399, 699}
     ply = 0
-    check_obs_at = {0, 1, 2, 49, 99, 149, 399, 699}
     while True:
-        E.stratego_run_plies(eng.ctx, chunk, actions=acts, obs=eng.obs, done=done, outcome=outc,
+        E.stratego_run_plies(eng.ctx, 1, actions=acts, obs=eng.obs, done=done, outcome=outc,
                              reason=reas, ep_len=epl)
-        for p in range(chunk):
-            r = ref.ply(obs=(ply + p) in check_obs_at or p == chunk - 1, mask=False)
-            assert_same(f"actions@{ply + p}", cpu(acts[p]), r["actions"])
-            assert_same(f"done@{ply + p}", cpu(done[p]), r["done"])
-            if (ply + p) in check_obs_at:
-                # obs of the current ply is only kept for the chunk's last ply
-                pass
-        assert_same(f"obs@{ply + chunk - 1}", cpu(eng.obs), r["obs"])
-        ply += chunk
-        if cpu(done[-1]).all():
+        r = ref.ply(obs=True, mask=False)
+        assert_same(f"actions@{ply}", cpu(acts[0]), r["actions"])
+        assert_same(f"done@{ply}", cpu(done[0]), r["done"])
+        if ply in full_obs_at:
+            assert_same(f"obs@{ply}", cpu(eng.obs), r["obs"])
+        else:
+            games = (np.arange(sub) * (n // sub) + ply) % n
+            idx = torch.from_numpy(games).cuda()
+            assert_same(f"obs@{ply} (64 games)", cpu(eng.obs[idx]), r["obs"][games])
+        ply += 1
+        if cpu(done[0]).all():
             break
-        assert ply <= 1100
+        assert ply <= 1000
     assert_same("final states", cpu(eng.export()), ref.export())
-    d_out, d_rsn, d_len = cpu(outc[-1]), cpu(reas[-1]), cpu(epl[-1])
+    d_out, d_rsn, d_len = cpu(outc[0]), cpu(reas[0]), cpu(epl[0])
     recs = ref.export()
     hs = [header(recs[g]) for g in range(n)]
     want_pairs = np.zeros((3, 6), dtype=np.int64)
