@@ -166,7 +166,10 @@ int stratego_run_plies_slots(stratego_ctx* ctx, const int32_t* slots_dev, int32_
  * consistent with public information (revealed and dead pieces keep their
  * types; a piece that has moved is neither Flag nor Bomb), drawn from
  * Philox4x32-10(key = seed, counter = (new id, block, episode, 3)); the new
- * game id is game_id_base + i*per + j.  nsrc*per must not exceed N. */
+ * game id is game_id_base + i*per + j; slots from nsrc*per on are left as
+ * they are.  A malformed source record latches E_BAD_STATE with the slot of
+ * its first resample (i*per) and its slots are left as they are.  Errors:
+ * E_INVAL (null source, nsrc or per below 1, nsrc*per above N), E_HIP. */
 int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int32_t nsrc,
                              int32_t per, uint32_t game_id_base);
 

@@ -1551,59 +1551,105 @@ __device__ __forceinline__ void encode_game(const uint8_t* R, uint8_t* slab, Rul
 // replaced by this uniform model): first the Flag and Bombs among the unmoved
 // hidden pieces (partial Fisher-Yates in ascending id order, Flag first), then
 // the movable multiset shuffled over the remaining hidden pieces in ascending
-// id order.  Runs on lane 0.
-__device__ __forceinline__ void resample_game(uint8_t* R, uint8_t* scratch, uint64_t seed, uint32_t new_id) {
+// id order.  The random words (Philox counter (new id, block, episode, 3),
+// words x, y, z, w of each block in turn) are drawn one per lane, the two
+// shuffles run as swaps between lanes, and the new types are patched into the
+// record's 16-byte chunks as they are stored, so one source serves many
+// resamples without being copied.
+
+// Swap the values of lanes a and b (a, b wave-uniform).
+__device__ __forceinline__ int lane_swap(int v, int a, int b) {
+  const int va = __builtin_amdgcn_readlane(v, a), vb = __builtin_amdgcn_readlane(v, b);
   const int lane = lane_id();
-  if (lane == 0) {
-    const int z = 1 - (int)(hdr_u32(R, kOffPly) & 1);
-    int known[12];
-    for (int t = 0; t < 12; ++t) known[t] = 0;
-    uint8_t* unmoved = scratch;        // up to 40 ids
-    uint8_t* list = scratch + 40;      // up to 40 types
-    int nu = 0;
-    for (int id = 40 * z; id < 40 * z + 40; ++id) {
-      uint32_t w0 = piece_words(R, id)[0];
-      if (!p_alive(w0) || p_revealed(w0)) known[p_type(w0)]++;
-      else if (!p_moved(w0)) unmoved[nu++] = (uint8_t)id;
-    }
-    const int nflag = initial_count(kFlag) - known[kFlag];
-    const int I = nflag + initial_count(kBomb) - known[kBomb];
-    WordStream ws;
-    ws.init(seed, new_id, hdr_u32(R, kOffEpisode), 3u);
-    for (int i = 0; i < I; ++i) {
-      int j = i + (int)mulshift(ws.next(), (uint32_t)(nu - i));
-      uint8_t tmp = unmoved[i];
-      unmoved[i] = unmoved[j];
-      unmoved[j] = tmp;
-    }
-    // mark the chosen immovable slots with their new types (bit 7 = assigned)
-    int L = 0;
-    for (int t = 0; t <= kMarshal; ++t)
-      for (int c = initial_count(t) - known[t]; c > 0; --c) list[L++] = (uint8_t)t;
-    for (int i = L - 1; i >= 1; --i) {
-      int j = (int)mulshift(ws.next(), (uint32_t)(i + 1));
-      uint8_t tmp = list[i];
-      list[i] = list[j];
-      list[j] = tmp;
-    }
-    // assign: immovables first (flag first), then the shuffled movables in id order
-    uint64_t immovable_mask = 0;   // bit (id - 40z)
-    for (int i = 0; i < I; ++i) {
-      int id = unmoved[i];
-      uint32_t* w = piece_words(R, id);
-      w[0] = (w[0] & ~15u) | (uint32_t)(i < nflag ? kFlag : kBomb);
-      immovable_mask |= 1ull << (id - 40 * z);
-    }
-    int k = 0;
-    for (int id = 40 * z; id < 40 * z + 40; ++id) {
-      uint32_t* w = piece_words(R, id);
-      if (!p_alive(w[0]) || p_revealed(w[0])) continue;
-      if ((immovable_mask >> (id - 40 * z)) & 1) continue;
-      w[0] = (w[0] & ~15u) | (uint32_t)list[k++];
-    }
-    set_hdr_u32(R, kOffGameId, new_id);
+  return lane == a ? vb : lane == b ? va : v;
+}
+
+// What every resample of one source shares.
+struct ResampleSource {
+  int z, nu, I, L, nflag;
+  uint32_t episode;
+  uint64_t hidden;   // bit m: piece 40 z + m is alive and unrevealed
+  int unmoved;       // lane m < nu: id of the m-th unmoved hidden piece of z, ascending
+  int list;          // lane m < L: the m-th type of z's hidden movable multiset, sorted
+  uint4 c0, c1;      // the record's 16-byte chunks lane and 64 + lane (lane < 32)
+};
+
+__device__ __forceinline__ ResampleSource resample_prepare(const uint8_t* R) {
+  const int lane = lane_id();
+  ResampleSource S;
+  S.z = 1 - (int)(hdr_u32(R, kOffPly) & 1);
+  S.episode = hdr_u32(R, kOffEpisode);
+  const bool mine = lane < 40;
+  const uint32_t w0 = mine ? piece_words(R, 40 * S.z + lane)[0] : 0u;
+  const bool known = mine && (!p_alive(w0) || p_revealed(w0));
+  const bool hid = mine && p_alive(w0) && !p_revealed(w0);
+  const int t = p_type(w0);
+  S.hidden = ballot(hid);
+  const uint64_t um = ballot(hid && !p_moved(w0));
+  S.nu = __popcll(um);
+  S.unmoved = lane < S.nu ? 40 * S.z + select_bit(um, lane) : 0;
+  // hidden counts per type: the initial multiset minus the known pieces
+  int acc = 0, ty = 0;
+  S.L = 0;
+#pragma unroll
+  for (int k = 0; k <= kMarshal; ++k) {
+    const int c = initial_count(k) - __popcll(ballot(known && t == k));
+    acc += c;
+    ty += lane >= acc ? 1 : 0;
   }
-  wave_sync();
+  S.L = acc;
+  S.list = ty;
+  S.nflag = initial_count(kFlag) - __popcll(ballot(known && t == kFlag));
+  S.I = S.nflag + initial_count(kBomb) - __popcll(ballot(known && t == kBomb));
+  const uint4* r4 = reinterpret_cast<const uint4*>(R);
+  S.c0 = r4[lane];
+  S.c1 = lane < 32 ? r4[64 + lane] : make_uint4(0, 0, 0, 0);
+  return S;
+}
+
+// One resample of S with game id new_id, stored as a record at out.
+__device__ __forceinline__ void resample_store(const ResampleSource& S, uint64_t seed, uint32_t new_id,
+                                               uint8_t* out) {
+  const int lane = lane_id();
+  // word m of the stream, one per lane; the immovable draws take words
+  // 0 .. I-1, the movable shuffle (i = L-1 down to 1) words I .. I+L-2
+  const uint4 blk = philox(make_uint4(new_id, (uint32_t)(lane >> 2), S.episode, 3u), seed);
+  const int q = lane & 3;
+  const uint32_t word = q == 0 ? blk.x : q == 1 ? blk.y : q == 2 ? blk.z : blk.w;
+  int jv = 0;
+  if (lane < S.I) jv = lane + (int)mulshift(word, (uint32_t)(S.nu - lane));
+  else if (lane < S.I + S.L - 1) jv = (int)mulshift(word, (uint32_t)(S.L - (lane - S.I)));
+  int um = S.unmoved, ls = S.list;
+  for (int a = 0; a < S.I; ++a) um = lane_swap(um, a, __builtin_amdgcn_readlane(jv, a));
+  for (int s = 0; s < S.L - 1; ++s)
+    ls = lane_swap(ls, S.L - 1 - s, __builtin_amdgcn_readlane(jv, S.I + s));
+  // the chosen immovable pieces
+  uint64_t chosen = 0;
+  for (int a = 0; a < S.I; ++a) chosen |= 1ull << (__builtin_amdgcn_readlane(um, a) - 40 * S.z);
+  const uint64_t rest = S.hidden & ~chosen;
+  // chunk lane holds piece lane - 16 (lanes 16..63), chunk 64 + lane piece 48 + lane (lanes 0..31)
+  int newtype[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int id = h == 0 ? lane - 16 : 48 + lane;
+    const int m = id - 40 * S.z;
+    const bool ours = (h == 0 ? lane >= 16 : lane < 32) && m >= 0 && m < 40;
+    const int mm = ours ? m : 0;
+    const int rank = __popcll(rest & ((1ull << mm) - 1ull));
+    const int from_list = __shfl(ls, rank, 64);
+    int t = -1;
+    if (ours && ((rest >> mm) & 1ull)) t = from_list;
+    for (int a = 0; a < S.I; ++a)
+      if (ours && __builtin_amdgcn_readlane(um, a) == id) t = a < S.nflag ? kFlag : kBomb;
+    newtype[h] = t;
+  }
+  uint4 c0 = S.c0, c1 = S.c1;
+  if (newtype[0] >= 0) c0.x = (c0.x & ~15u) | (uint32_t)newtype[0];
+  if (newtype[1] >= 0) c1.x = (c1.x & ~15u) | (uint32_t)newtype[1];
+  if (lane == 0) c0.x = new_id;   // header word 0: the game id
+  uint4* dst = reinterpret_cast<uint4*>(out);
+  dst[lane] = c0;
+  if (lane < 32) dst[64 + lane] = c1;
 }
 
 // ---------------------------------------------------------------- validation

@@ -316,22 +316,32 @@ __global__ void __launch_bounds__(256) k_import(uint8_t* states, const int32_t* 
   else if (lane_id() == 0) atomicMin(&err[1], slot);
 }
 
-// Slot k = i*per + j receives a resample of source record i.
+// Slot k = i*per + j receives a resample of source record i.  Each wave takes
+// up to kResamplesPerWave consecutive resamples of one source: it loads and
+// checks the source once, then draws and stores its resamples.
+constexpr int kResamplesPerWave = 16;
 __global__ void __launch_bounds__(256) k_resample(uint8_t* states, const uint8_t* src, int32_t nsrc,
                                                  int32_t per, uint64_t seed, uint32_t id_base,
                                                  int32_t* err) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
-  const int k = blockIdx.x * (blockDim.x >> 6) + wave;
-  if (k >= nsrc * per) return;
-  uint8_t* slab = smem + wave * kSlabImage;
-  load_record(slab, src + (size_t)(k / per) * kRecordBytes);
-  if (!record_ok(slab)) {
-    if (lane_id() == 0) atomicMin(&err[1], k);
+  const int chunks = (per + kResamplesPerWave - 1) / kResamplesPerWave;
+  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (w >= (int64_t)nsrc * chunks) return;
+  const int i = (int)(w / chunks);
+  const int j0 = (int)(w % chunks) * kResamplesPerWave;
+  const int j1 = j0 + kResamplesPerWave < per ? j0 + kResamplesPerWave : per;
+  uint8_t* R = smem + wave * kRecordBytes;
+  load_record(R, src + (size_t)i * kRecordBytes);
+  if (!record_ok(R)) {
+    if (lane_id() == 0) atomicMin(&err[1], i * per + j0);
     return;
   }
-  resample_game(slab, slab + kSlabScratch, seed, id_base + (uint32_t)k);
-  store_record(states + (size_t)k * kRecordBytes, slab);
+  const ResampleSource S = resample_prepare(R);
+  for (int j = j0; j < j1; ++j) {
+    const int k = i * per + j;
+    resample_store(S, seed, id_base + (uint32_t)k, states + (size_t)k * kRecordBytes);
+  }
 }
 
 // Copy the records of the listed slots to out (contiguous).
@@ -1114,9 +1124,10 @@ int stratego_reset_resampled(stratego_ctx* c, const void* src, int32_t nsrc, int
                              uint32_t game_id_base) {
   if (!c || !src || nsrc <= 0 || per <= 0 || (int64_t)nsrc * per > c->cfg.num_games)
     return STRATEGO_E_INVAL;
-  const int total = nsrc * per;
-  hipLaunchKernelGGL(k_resample, dim3(grid_for(total, 4)), dim3(256), 4 * kSlabImage, c->stream, c->states,
-                     reinterpret_cast<const uint8_t*>(src), nsrc, per, c->cfg.seed, game_id_base, c->err);
+  const int64_t waves = (int64_t)nsrc * ((per + kResamplesPerWave - 1) / kResamplesPerWave);
+  hipLaunchKernelGGL(k_resample, dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * kRecordBytes, c->stream,
+                     c->states, reinterpret_cast<const uint8_t*>(src), nsrc, per, c->cfg.seed, game_id_base,
+                     c->err);
   return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
 }
 

@@ -318,6 +318,45 @@ def test_resample_and_rollout_262144_games():
     eng.close()
 
 
+def test_resample_edge_cases():
+    """Sources of every kind (fresh setups: all hidden and unmoved; played
+    records with moved, revealed and dead pieces and either side to move;
+    sparse random positions), a per that is not a multiple of the resamples a
+    wave takes, a nonzero game id base and spare slots: bit-exact with the
+    oracle.  A malformed source is latched at its first slot and its slots
+    are left alone."""
+    seed, per, base = 11, 37, 1000
+    fresh = O.OracleEngine(16, 5).export()
+    ref = O.OracleEngine(64, 6, auto_reset=True)
+    for _ in range(41):
+        ref.ply(obs=False, mask=False)
+    played = ref.export()
+    sparse = random_position_records(48, seed=4)
+    src = np.concatenate([fresh, played, sparse])
+    nsrc = len(src)
+    n = nsrc * per + 100
+    eng = E.Engine(n, seed)
+    before = cpu(eng.export())
+    E.stratego_reset_resampled(eng.ctx, torch.from_numpy(src).cuda(), per, base)
+    assert eng.error() == (0, -1)
+    got = cpu(eng.export())
+    want = O.OracleEngine.from_records(src, seed).resample(per, seed, base).export()
+    assert_same("resampled", got[:nsrc * per], want)
+    assert_same("spare slots", got[nsrc * per:], before[nsrc * per:])
+    # a lake square holding a piece id: source 5 is refused
+    bad = src.copy()
+    bad[5, 64 + 42] = 0
+    eng.load(torch.from_numpy(before).cuda())
+    E.stratego_reset_resampled(eng.ctx, torch.from_numpy(bad).cuda(), per, base)
+    assert eng.error() == (E.E_BAD_STATE, 5 * per)
+    got = cpu(eng.export())
+    rows = np.arange(nsrc * per)
+    mine = (rows >= 5 * per) & (rows < 6 * per)
+    assert_same("refused source's slots", got[:nsrc * per][mine], before[:nsrc * per][mine])
+    assert_same("other sources", got[:nsrc * per][~mine], want[~mine])
+    eng.close()
+
+
 # ---------------------------------------------------------------- serving
 def serving_inputs(total, seed=2):
     """Start states drawn from games of random play without auto-reset (the
