@@ -79,7 +79,10 @@ __host__ __device__ __forceinline__ constexpr int wave_lds_bytes(int layout) { r
 // only the record, the work areas and the to-square sets (4.9 KB of LDS per
 // wave with the spare record), so with a 128-VGPR budget (no spills) a CU
 // holds 16 of their waves instead of the 8 the both-observer encoder allows:
-// 25% faster plies at 65,536 games, 36% at 262,144.
+// 25% faster plies at 65,536 games, 36% at 262,144.  Register budgets: the
+// both-observer encoder is LDS-bound at 2 waves per SIMD anyway, so it may
+// use 256 VGPRs; the one-observer encoder runs best at 3 (168 VGPRs, no
+// spills; 4% faster than 4 waves with 128 and spills); the rest at 4.
 constexpr int kEncNone = 3;
 constexpr int kNoObsSlabBytes = kSlabImage + kDestSetBytes;
 __host__ __device__ __forceinline__ constexpr int ply_slab_bytes(int enc, int layout) {
@@ -92,7 +95,7 @@ static_assert(kNoObsSlabBytes % 16 == 0, "record buffers stay 16-byte aligned");
 
 template <int MODE, int ENC>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : 4))) k_ply(PlyArgs a) {
+__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : 4))) k_ply(PlyArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
   uint8_t* slab = smem + wave * ply_wave_lds_bytes(ENC, a.layout);
@@ -838,7 +841,11 @@ int enqueue_plies(stratego_ctx* c, hipStream_t s, int32_t nplies, const int32_t*
     a.reason = reason;
     a.ep_len = ep_len;
     a.ts = timed ? c->ts + 2 * p : nullptr;
-    a.tickets = c->tickets + p;
+    // plies with observations hand out tiles in address order from a ticket
+    // counter (11% faster than a static split: the games written at any time
+    // stay adjacent); observation-free plies split statically, since there a
+    // ticket's round trip waits on the wave's outstanding stores (25% faster)
+    a.tickets = obs ? c->tickets + p : nullptr;
     if (record) set_hist(c, a, p);
     int rc = launch_ply(c, s, kFused, a, G, S, true, obs == nullptr);
     if (rc != STRATEGO_OK) return rc;
