@@ -373,6 +373,20 @@ def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
     ended = float((done[-1] != 0).float().mean())
     assert eng.error() == (0, -1)
     eng.close()
+    # the same load with magnet-policy rollouts (section 2.3), the paper's
+    # rollout policy before a network is trained
+    eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=False, sampler=E.SAMPLER_MAGNET)
+    load()
+    magnet_ms = []
+    for _ in range(reps):
+        E.stratego_reset_resampled(eng.ctx, src, per, 0)
+        ev[1].record(stream)
+        E.stratego_run_plies(eng.ctx, plies, done=done, outcome=outc, use_graph=True)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        magnet_ms.append(ev[1].elapsed_time(ev[2]))
+    assert eng.error() == (0, -1)
+    eng.close()
     r, w = min(res_ms), min(roll_ms)
     # resample: each new record (1536 B) written, its source read once per
     # game from cache; rollout ply: record read + written, done + outcome
@@ -381,6 +395,8 @@ def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
                rollout_ms=w, rollout_ms_per_ply=w / plies,
                rollout_game_steps_per_s=n * plies / (w / 1e3), total_ms=r + w,
                resampled_states_per_s=n / (r / 1e3), ended_within_50_plies=ended,
+               magnet_rollout_ms=min(magnet_ms),
+               magnet_rollout_game_steps_per_s=n * plies / (min(magnet_ms) / 1e3),
                workload=f"{n_src} ply-100 states x {per} resamples, {plies} random plies each "
                         "(no observations), best of {reps} runs".replace("{reps}", str(reps)))
     print(f"[bench] search-shaped load: {out}", file=sys.stderr, flush=True)

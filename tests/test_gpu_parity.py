@@ -357,6 +357,34 @@ def test_resample_edge_cases():
     eng.close()
 
 
+def test_resample_then_magnet_rollouts():
+    """The search-shaped load with magnet-policy rollouts (section 2.3): 64
+    mid-game states x 16 resamples, 50 plies in a captured graph, every
+    record after the rollout and the last ply's outcomes equal the oracle's."""
+    seed, per, plies = 13, 16, 50
+    src_eng = O.OracleEngine(256, seed, k_battleless=100, max_moves=1000)
+    for _ in range(60):
+        src_eng.ply(obs=False, mask=False)
+    recs = src_eng.export()
+    alive = [g for g in range(256) if header(recs[g])["done"] == 0][:64]
+    src = recs[alive]
+    n = len(src) * per
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, sampler=E.SAMPLER_MAGNET)
+    E.stratego_reset_resampled(eng.ctx, torch.from_numpy(src).cuda(), per, 0)
+    done = torch.empty((plies, n), dtype=torch.int8, device="cuda")
+    outc = torch.empty((plies, n), dtype=torch.int8, device="cuda")
+    E.stratego_run_plies(eng.ctx, plies, done=done, outcome=outc, use_graph=True)
+    ref = O.OracleEngine.from_records(src, seed, max_moves=1000, sampler=O.SAMPLER_MAGNET).resample(per, seed)
+    for _ in range(plies - 1):
+        ref.ply(obs=False, mask=False)
+    r = ref.ply(obs=False, mask=False)
+    assert_same("states after magnet rollouts", cpu(eng.export()), ref.export())
+    assert_same("done", cpu(done[-1]), r["done"])
+    assert_same("outcome", cpu(outc[-1]), r["outcome"])
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
 # ---------------------------------------------------------------- serving
 def serving_inputs(total, seed=2):
     """Start states drawn from games of random play without auto-reset (the
