@@ -25,9 +25,17 @@
  *     12-35 and 41-42 hold round(255*x) of a probability or fraction; channels
  *     456-487 hold 0x01 at a move's destination and 0xFF (int8 -1) at its
  *     source (App. C).
- *   - A game state is a canonical 1536-byte record (layout in the project
- *     documentation); records are the checkpoint format: importing an exported
- *     record continues the game bit-exactly.
+ *   - A game state is a canonical 1536-byte record, little-endian: u32 game
+ *     id at 0, u32 episode at 4, i32 ply at 8, i32 battleless moves at 12, u8
+ *     move-ring count at 16, u8 done at 17, i8 outcome at 18, u8 reason at 19,
+ *     u32 redraws at 20; per player p the two-square state at 24 + 8p (u8
+ *     piece id, u8 square count 0 or 2-4, u8 squares[4]); u8 chase length at
+ *     40 and u8 chasing player at 41; i8 board[100] at 64 (piece id, -1
+ *     empty, -2 lake); u8 ring[32][2] of (from, to) at 164, the move of ply t
+ *     in slot t mod 32; at 256 + 16 id four u32 words per piece id (0-39 red,
+ *     40-79 blue): type, alive, revealed, moved, death cause and square, and
+ *     the history-feature bits of App. C.1.  Records are the checkpoint
+ *     format: importing an exported record continues the game bit-exactly.
  *   - Every device pointer must be device memory on the context's device.
  *     The caller owns all buffers it passes; the library owns the game states
  *     (allocated once in stratego_init).
@@ -100,8 +108,12 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
  * for search).  slots_dev: int32[n] slot indices, or NULL for slots 0..n-1.
  * states_dev: NULL = fresh uniform setups with episode 0 (a setup that is
  * already terminal is redrawn when auto_reset is on); otherwise n canonical
- * records copied into the slots.  A malformed record (see the record checks in
- * the project documentation) or a slot outside [0, N) latches E_BAD_STATE in
+ * records copied into the slots.  A malformed record (lakes not exactly on
+ * the lake squares, a board entry out of range or naming a dead piece, an
+ * alive piece not on exactly one square, a player's types not the initial
+ * multiset, a moved Flag or Bomb, a dead piece unrevealed or with a bad death
+ * cause or square, ring squares or counters out of range, malformed
+ * two-square or chase state) or a slot outside [0, N) latches E_BAD_STATE in
  * the error word (see stratego_get_error) and leaves that slot unchanged. */
 int stratego_reset(stratego_ctx* ctx, const int32_t* slots_dev, int32_t n, const void* states_dev);
 

@@ -816,8 +816,11 @@ static void encode(const orc_state* st, const orc_cfg* cfg, int o, uint8_t* out)
 }
 
 /* ------------------------------------------------------------------ */
-/* Canonical state record: 1536 bytes, little-endian (layout written out in
- * the project documentation; serialised here independently). */
+/* Canonical state record: 1536 bytes, little-endian, the interchange format
+ * of the public interface (header fields at 0-23, per-player two-square
+ * state at 24 + 8p, chase length and chaser at 40-41, board at 64, move ring
+ * at 164, four 32-bit words per piece id at 256 + 16 id), serialised here on
+ * its own. */
 #define REC_BYTES 1536
 
 static void put_u32(uint8_t* b, int off, uint32_t v) {
