@@ -141,22 +141,26 @@ int stratego_sample_actions(stratego_ctx* ctx, const uint64_t* mask_dev,
 int stratego_step(stratego_ctx* ctx, const int16_t* actions_dev, int8_t* done_dev,
                   int8_t* outcome_dev, uint8_t* reason_dev, int16_t* ep_len_dev);
 
-/* Information states of both players (App. C): obs_dev uint8[N][2][488][10][10]. */
+/* Information states of both players (App. C): obs_dev uint8[N][2][488][10][10]
+ * (with acting_obs_only, uint8[N][1][488][10][10]: the acting player's).
+ * Errors: E_INVAL (NULL obs_dev). */
 int stratego_encode_obs(stratego_ctx* ctx, uint8_t* obs_dev);
 
 /* Copy the N canonical records (1536 bytes each) to states_dev (device). */
 int stratego_export_states(stratego_ctx* ctx, void* states_dev);
 
 /* Fused engine (one persistent kernel per ply): for each of nplies plies and
- * every game, legal mask -> uniform sample -> encode both players' obs of the
- * pre-move state -> step (with the context's auto-reset).  The per-ply
+ * every game, legal mask -> sample (the context's sampler) -> encode the
+ * observations of the pre-move state (both players, or the acting player's
+ * with acting_obs_only) -> step (with the context's auto-reset).  The per-ply
  * outputs mask_dev, num_legal_dev and obs_dev are overwritten each ply (they
  * hold the last ply's values); actions/done/outcome/reason/ep_len are written
  * per ply as [nplies][N] arrays.  Any output may be NULL (obs_dev NULL skips
  * the encoding).  With use_graph = 1 the nplies launches are captured once
  * into a hipGraph (per distinct argument set) and replayed.  ply_ns_dev, if
  * not NULL, receives int64[nplies] per-ply device durations in nanoseconds
- * (first wave start to last wave end). */
+ * (first wave start to last wave end).  Errors: E_INVAL (nplies < 0; nplies
+ * above 64 with use_graph or ply_ns_dev), E_HIP. */
 int stratego_run_plies(stratego_ctx* ctx, int32_t nplies, uint64_t* mask_dev,
                        int16_t* num_legal_dev, int16_t* actions_dev, uint8_t* obs_dev,
                        int8_t* done_dev, int8_t* outcome_dev, uint8_t* reason_dev,
@@ -166,7 +170,8 @@ int stratego_run_plies(stratego_ctx* ctx, int32_t nplies, uint64_t* mask_dev,
  * int32[nslots] (distinct, each in [0, N); an out-of-range entry is skipped
  * and latches E_BAD_STATE with its list position); per-game outputs are
  * indexed by position in the slot list ([nplies][nslots], obs
- * [nslots][2][488][100]).  No graph. */
+ * [nslots][2 or 1][488][100]).  No graph.  Errors: E_INVAL (NULL slots_dev,
+ * nslots outside [0, N], nplies < 0, a rollout buffer present), E_HIP. */
 int stratego_run_plies_slots(stratego_ctx* ctx, const int32_t* slots_dev, int32_t nslots,
                              int32_t nplies, uint64_t* mask_dev, int16_t* actions_dev,
                              uint8_t* obs_dev, int8_t* done_dev, int8_t* outcome_dev,
@@ -188,14 +193,15 @@ int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int3
 /* Serving (continuous batching).  A request asks for `plies` fused plies of
  * num_games games whose canonical records sit at rows [first, first +
  * num_games) of in_states_dev.  Kinds: STRATEGO_REQ_STEP (plies must be 1; the
- * observations of both players of the input states are written to obs_out_dev
+ * observations of the input states (both players, or the acting player's with
+ * acting_obs_only) are written to obs_out_dev
  * at rows first + j, or at the game's pool slot when obs_by_slot = 1) and
  * STRATEGO_REQ_ROLLOUT (no observations).  The context's N slots are the
  * device-resident pool.  Requests are admitted first come first served, as
  * soon as they have arrived (realtime = 1: at arrival_s seconds after the call
  * starts; realtime = 0: all at once) and both enough free slots and enough of
- * the memory budget remain (a game reserves 1536 bytes, plus 97600 for step
- * requests); mem_budget_bytes <= 0 uses the device's free memory at the start
+ * the memory budget remain (a game reserves 1536 bytes, plus its observation
+ * bytes, 97600 or 48800, for step requests); mem_budget_bytes <= 0 uses the device's free memory at the start
  * of the call.  Every iteration runs one fused ply over all admitted games, so
  * requests that arrive while others run join them on the device; a request
  * leaves after its last ply, when its final records are copied to rows
@@ -282,7 +288,8 @@ int stratego_history_legal_mask(stratego_ctx* ctx, int64_t t, const int32_t* gam
 
 /* ComputeInfostateTensor(t) of App. B.1: obs_dev uint8[count][2][488][10][10],
  * both players' information states (App. C) at time step t, as
- * stratego_encode_obs would have returned then. */
+ * stratego_encode_obs would have returned then (uint8[count][1][488][10][10],
+ * the acting player's, with acting_obs_only). */
 int stratego_history_encode_obs(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
                                 uint8_t* obs_dev);
 
