@@ -160,7 +160,7 @@ int stratego_export_states(stratego_ctx* ctx, void* states_dev);
  * into a hipGraph (per distinct argument set) and replayed.  ply_ns_dev, if
  * not NULL, receives int64[nplies] per-ply device durations in nanoseconds
  * (first wave start to last wave end).  Errors: E_INVAL (nplies < 0; nplies
- * above 64 with use_graph or ply_ns_dev), E_HIP. */
+ * above 4096 with use_graph or ply_ns_dev), E_HIP. */
 int stratego_run_plies(stratego_ctx* ctx, int32_t nplies, uint64_t* mask_dev,
                        int16_t* num_legal_dev, int16_t* actions_dev, uint8_t* obs_dev,
                        int8_t* done_dev, int8_t* outcome_dev, uint8_t* reason_dev,
