@@ -209,3 +209,32 @@ def test_65536_games_ring_against_live_outputs_and_sampled_oracle():
         assert_same(f"obs t={t}", cpu(eng.obs_at(t, g)), ref.encode())
     assert eng.error() == (0, -1)
     eng.close()
+
+
+def test_acting_player_views_at_past_steps():
+    """With acting_obs_only the ring re-materialises the acting player's view
+    ([count, 1, 488, 10, 10]) at every step of the window, equal to the live
+    outputs of the plies and to the oracle's."""
+    n, seed, H = 200, 8, 5
+    kw = dict(k_battleless=15, max_moves=80, auto_reset=True)
+    eng = E.Engine(n, seed, history_len=H, acting_obs=True, **kw)
+    buf = O.OracleRolloutBuffer(O.OracleEngine(n, seed, acting_obs=True, **kw), H)
+    live = []
+    for ply in range(7):
+        E.stratego_run_plies(eng.ctx, 1, obs=eng.obs)
+        r = buf.ply(obs=True)
+        assert_same(f"obs@{ply}", cpu(eng.obs), r["obs"])
+        live.append(eng.obs.clone())
+    lo, T = eng.window()
+    assert (lo, T) == (2, 7)
+    games = [0, 199, 17, 17, 100]
+    g_dev = torch.tensor(games, dtype=torch.int32, device="cuda")
+    for t in range(lo, T + 1):
+        got = eng.obs_at(t)
+        assert got.shape == (n, 1, 488, 10, 10)
+        assert_same(f"obs at {t}", cpu(got), buf.obs_at(t))
+        assert_same(f"obs at {t} (list)", cpu(eng.obs_at(t, g_dev)), buf.obs_at(t, games))
+        if t < T:
+            assert torch.equal(got, live[t])
+    assert eng.error() == (0, -1)
+    eng.close()
