@@ -251,7 +251,7 @@ def two_square_bench(E, torch, n=GAMES, warm=256, timed=128):
 
 
 def policy_bench(E, torch, n=GAMES, warm=256, timed=128):
-    """Section 2.3 / App. D.7 at the headline size: the fused ply with the
+    """Sections 2.4-2.5 / App. D.7 at the headline size: the fused ply with the
     magnet sampler, and the legal-list policy kernels (magnet probabilities,
     the search policy with the paper's alpha = 0.002, beta = 0.02, and the
     sampler over it) on 65,536 mid-game positions."""
@@ -373,7 +373,7 @@ def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
     ended = float((done[-1] != 0).float().mean())
     assert eng.error() == (0, -1)
     eng.close()
-    # the same load with magnet-policy rollouts (section 2.3), the paper's
+    # the same load with magnet-policy rollouts (section 2.4), the paper's
     # rollout policy before a network is trained
     eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=False, sampler=E.SAMPLER_MAGNET)
     load()

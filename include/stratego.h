@@ -88,7 +88,7 @@ typedef struct {
   int32_t two_square_rule; /* 1: a piece may not cross the same square boundary on more than
                               three consecutive turns of its owner (App. A, App. B.2) */
   int32_t sampler;         /* move sampler of stratego_sample_actions and the fused plies:
-                              0 uniform over legal actions; 1 magnet policy (section 2.3: a
+                              0 uniform over legal actions; 1 magnet policy (section 2.4: a
                               piece with a legal move uniformly, then one of its moves) */
   int32_t chasing_rule;    /* 1: continuous-chasing rule (App. A, Table "chase", App. B.3): the
                               chasing player may not make a threat that recreates a position
@@ -345,7 +345,7 @@ int stratego_history_info(stratego_ctx* ctx, int64_t t, const int32_t* games_dev
 int stratego_history_export(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
                             void* states_dev);
 
-/* Policies over legal lists (section 2.3 and App. D.7).  A game's legal list
+/* Policies over legal lists (sections 2.4-2.5 and App. D.7).  A game's legal list
  * is its acting player's legal actions in ascending order, padded to
  * STRATEGO_MAX_LEGAL entries with -1 (finished games: all -1).  Per-action
  * arrays are float[N][256] aligned with the list; entries past num_legal are
@@ -354,7 +354,7 @@ int stratego_history_export(stratego_ctx* ctx, int64_t t, const int32_t* games_d
 /* actions_dev int16[N][256]: the legal lists; num_legal_dev int16[N] or NULL. */
 int stratego_legal_list(stratego_ctx* ctx, int16_t* actions_dev, int16_t* num_legal_dev);
 
-/* The magnet policy rho (section 2.3 / App. D: a piece with a legal move
+/* The magnet policy rho (section 2.4 / App. D.4: a piece with a legal move
  * uniformly at random, then one of its legal moves uniformly at random):
  * probs_dev float[N][256], rho = 1 / (P * m) as one IEEE single division,
  * P = pieces with a legal move, m = legal moves of the listed action's piece. */

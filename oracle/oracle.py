@@ -228,7 +228,7 @@ class OracleEngine:
                             _p(r["reason"]), _p(r["ep_len"]))
         return r
 
-    # -- policies over the legal list (section 2.4, App. D.7) ---------------
+    # -- policies over the legal list (sections 2.4-2.5, App. D.7) ---------------
     def legal_actions_list(self):
         """Legal actions of every game in ascending order, padded with -1."""
         a = np.zeros((self.n, MAX_LEGAL), dtype=np.int16)

@@ -1023,7 +1023,7 @@ static int sample_one(const orc_state* st, const orc_cfg* cfg, const uint64_t* m
     uint32_t w[4];
     philox_block(cfg->seed, st->game_id, (uint32_t)st->ply, st->episode, TAG_MOVE, w);
     if (cfg->sampler == SAMPLER_MAGNET) {
-        /* the magnet policy (section 2.3, App. D: a movable piece uniformly at
+        /* the magnet policy (section 2.4, App. D.4: a movable piece uniformly at
          * random, then one of its legal moves uniformly at random): the
          * r1-th piece with a legal move in ascending square order, r1 =
          * bounded(y, P), then its r2-th move in ascending destination order,
@@ -1188,7 +1188,7 @@ void orc_batch_ply(orc_state* s, int n, const orc_cfg* cfg, uint64_t* mask, int1
 }
 
 /* ------------------------------------------------------------------ */
-/* Policies over the legal list (section 2.4, App. D.7).  A game's legal list
+/* Policies over the legal list (sections 2.4-2.5, App. D.7).  A game's legal list
  * is its legal actions in ascending order, padded to MAX_LEGAL with -1.    */
 #define MAX_LEGAL 256
 

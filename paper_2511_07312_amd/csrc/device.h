@@ -676,7 +676,7 @@ __device__ __forceinline__ int sample_from_words(const uint64_t w[3], int n, uin
   return -1;
 }
 
-// Magnet policy sample (section 2.3, App. D: a movable piece uniformly at
+// Magnet policy sample (section 2.4, App. D.4: a movable piece uniformly at
 // random, then one of its legal moves uniformly at random).  (lo0, hi0) is
 // the destination set of square lane, (lo1, hi1) that of square lane + 64
 // (zero beyond 99).  Same Philox block as the uniform sampler: r1 =

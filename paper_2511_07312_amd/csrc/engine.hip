@@ -534,7 +534,7 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs h) {
 }
 
 // ---------------------------------------------------------------- policies over legal lists
-// Section 2.3 / App. D (magnet policy) and App. D.7 (search policy).  A
+// Section 2.4 / App. D.4 (magnet policy) and section 2.5 / App. D.7 (search policy).  A
 // game's legal list is its legal actions in ascending order, padded to
 // kMaxLegal with -1; per-action inputs and outputs are aligned with it.
 enum : int { kPList = 0, kPMagnet = 1, kPSearch = 2, kPSample = 3 };

@@ -479,7 +479,7 @@ class Engine:
     def error(self):
         return stratego_get_error(self.ctx)
 
-    # policies over legal lists (section 2.3, App. D.7)
+    # policies over legal lists (sections 2.4-2.5, App. D.7)
     def legal_list(self):
         a = torch.empty((self.n, MAX_LEGAL), dtype=torch.int16, device=self.device)
         nl = torch.empty(self.n, dtype=torch.int16, device=self.device)

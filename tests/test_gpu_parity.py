@@ -358,7 +358,7 @@ def test_resample_edge_cases():
 
 
 def test_resample_then_magnet_rollouts():
-    """The search-shaped load with magnet-policy rollouts (section 2.3): 64
+    """The search-shaped load with magnet-policy rollouts (section 2.4): 64
     mid-game states x 16 resamples, 50 plies in a captured graph, every
     record after the rollout and the last ply's outcomes equal the oracle's."""
     seed, per, plies = 13, 16, 50

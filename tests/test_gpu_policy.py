@@ -1,4 +1,4 @@
-"""Magnet policy and search policy (section 2.3, App. D.7) on the GPU vs the
+"""Magnet policy and search policy (sections 2.4-2.5, App. D.7) on the GPU vs the
 oracle: legal lists, magnet probabilities, magnet sampling (plain and fused,
 with and without the two-square rule) and the policy sampler bit-exact; the
 single-precision search policy within the tolerance derived in the design

@@ -760,7 +760,7 @@ def test_two_square_can_leave_no_legal_move():
 
 
 # ---------------------------------------------------------------- magnet policy and search policy
-# Section 2.3 / App. D: the magnet policy rho picks a movable piece uniformly
+# Section 2.4 / App. D.4: the magnet policy rho picks a movable piece uniformly
 # at random, then one of its legal moves uniformly at random.  App. D.7: the
 # search plays pi_search = argmax <q, pi> - alpha KL(pi, rho) - beta KL(pi, pi_theta).
 def _replicate(rec, n):
