@@ -77,12 +77,13 @@ __host__ __device__ __forceinline__ constexpr int wave_lds_bytes(int layout) { r
 // 2 bit planes of one observer at a time (layout 7), 3 no observations: plies
 // that only mask, sample and step (rollouts, recording plies).  Those need
 // only the record, the work areas and the to-square sets (4.9 KB of LDS per
-// wave with the spare record), so with a 128-VGPR budget (no spills) a CU
-// holds 16 of their waves instead of the 8 the both-observer encoder allows:
-// 25% faster plies at 65,536 games, 36% at 262,144.  Register budgets: the
-// both-observer encoder is LDS-bound at 2 waves per SIMD anyway, so it may
-// use 256 VGPRs; the one-observer encoder runs best at 3 (168 VGPRs, no
-// spills; 4% faster than 4 waves with 128 and spills); the rest at 4.
+// wave with the spare record), so a CU holds 20 of their waves (5 per SIMD,
+// 96 VGPRs with a few spilled) instead of the 8 the both-observer encoder
+// allows.  Register budgets: the both-observer encoder is LDS-bound at 2
+// waves per SIMD anyway, so it may use 256 VGPRs; the one-observer encoder
+// runs best at 3 (168 VGPRs, no spills; 4% faster than 4 waves with 128 and
+// spills); the observation-free variant at 5 (5% faster than 4 waves with
+// 128 VGPRs; 6 and 8 waves spill too much); the byte-image layouts at 4.
 constexpr int kEncNone = 3;
 constexpr int kNoObsSlabBytes = kSlabImage + kDestSetBytes;
 __host__ __device__ __forceinline__ constexpr int ply_slab_bytes(int enc, int layout) {
@@ -95,7 +96,7 @@ static_assert(kNoObsSlabBytes % 16 == 0, "record buffers stay 16-byte aligned");
 
 template <int MODE, int ENC>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : 4))) k_ply(PlyArgs a) {
+__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone ? 5 : 4))) k_ply(PlyArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
   uint8_t* slab = smem + wave * ply_wave_lds_bytes(ENC, a.layout);
