@@ -1,9 +1,10 @@
 """Python binding of libstratego.so (argument marshalling only).
 
 Every function mirrors the C call of the same name in include/stratego.h.
-Device buffers are torch tensors on the GPU; the HIP stream is torch's
-current stream.  All game computation happens in the library's kernels: if the
-library is missing the import fails loudly, there is no CPU fallback.
+Device buffers are torch tensors on the GPU; a context runs on torch's
+current stream at the time it is created.  All game computation happens in the
+library's kernels: the library is loaded on first use, a missing library
+raises an error there, and there is no CPU fallback.
 """
 import ctypes
 import os
