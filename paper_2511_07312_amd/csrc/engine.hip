@@ -3,8 +3,9 @@
 // Plain engine: one launch per call (legal mask, sample, step, encode), one
 // wavefront per game, four games per 256-thread workgroup.
 // Fused engine: one persistent kernel per ply (mask -> sample -> encode ->
-// step), grid sized to the device's occupancy, tiles of G consecutive games
-// per workgroup, plies optionally replayed from a captured hipGraph.
+// step), grid sized to the device's occupancy, each wave working through
+// tiles of G consecutive games, plies optionally replayed from a captured
+// hipGraph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,7 +48,7 @@ struct PlyArgs {
   int16_t* ep_len;
   int32_t* err;
   unsigned long long* ts;
-  unsigned int* tickets;   // this ply's work counter (persistent launches), else NULL
+  unsigned int* tickets;   // this ply's work counter (plies with observations), else NULL
   // rollout buffer: record and step outcome of every stepped game at
   // row *hist_slot of the ring (NULL: not recorded)
   uint8_t* hist;
@@ -111,9 +112,9 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   const int G = a.games_per_tile;
   const int ntiles = (a.n + G - 1) / G;
   // Work distribution: every wave works through tiles of G consecutive games
-  // of its own.  With a ticket counter (persistent launches) a wave takes the
-  // next tile in address order whenever it becomes free; otherwise wave w of
-  // workgroup b takes tiles bW+w, bW+w+gridDim.x*W, ...
+  // of its own.  With a ticket counter (persistent plies with observations) a
+  // wave takes the next tile in address order whenever it becomes free;
+  // otherwise wave w of workgroup b takes tiles bW+w, bW+w+gridDim.x*W, ...
   const bool dynamic = a.tickets != nullptr;
   const int workers = gridDim.x * W;
   auto grab = [&]() -> int {
@@ -737,8 +738,9 @@ const void* fused_kernel(int enc) {
                   : reinterpret_cast<const void*>(&k_ply<kFused, 0>);
 }
 
-// grow: observation-free plies, where a game is short next to a ticket round
-// trip; the tile grows up to 8 games while every wave still gets two or more.
+// grow: observation-free plies, where a game is short next to the loop's
+// fixed costs; the tile grows up to 8 games while every wave still gets two
+// or more.
 int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent,
                bool grow = false) {
   // fused plies without observations take the observation-free variant,
