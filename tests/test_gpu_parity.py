@@ -192,6 +192,25 @@ def test_4096_games_to_terminal_histograms():
     eng.close()
 
 
+@pytest.mark.parametrize("n", [1, 7, 65, 1000, 5121, 20483])
+def test_observation_free_plies_at_ragged_sizes(n):
+    """The observation-free variant splits games statically and grows its
+    tiles with N: odd sizes around the tile and wave counts, direct and from a
+    graph, every ply's actions and the final states against the oracle."""
+    seed = 31 + n
+    eng = E.Engine(n, seed, k_battleless=20, max_moves=120, auto_reset=True)
+    ref = O.OracleEngine(n, seed, k_battleless=20, max_moves=120, auto_reset=True)
+    acts = torch.empty((8, n), dtype=torch.int16, device="cuda")
+    for rnd in range(4):
+        E.stratego_run_plies(eng.ctx, 8, actions=acts, use_graph=rnd % 2 == 1)
+        for p in range(8):
+            r = ref.ply(obs=False, mask=False)
+            assert_same(f"actions@{rnd}.{p}", cpu(acts[p]), r["actions"])
+    assert_same("states", cpu(eng.export()), ref.export())
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
 # ---------------------------------------------------------------- imported states
 def random_position_records(count, seed=0):
     from test_oracle_pins import random_position
