@@ -403,6 +403,36 @@ def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
     return out
 
 
+def other_seeds_bench(E, torch, G, S, n=GAMES, seeds=(2, 3), warm=1024, timed=640):
+    """The headline workload with other seeds (shorter runs, the tuned tiling):
+    the rate does not depend on the seed."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for seed in seeds:
+        eng = E.Engine(n, seed, K_BATTLELESS, MAX_MOVES, auto_reset=True)
+        E.stratego_set_tiling(eng.ctx, G, S)
+        obs = eng.obs
+
+        def plies():
+            E.stratego_run_plies(eng.ctx, GRAPH_PLIES, mask=eng.mask, obs=obs, use_graph=True)
+        for _ in range(warm // GRAPH_PLIES):
+            plies()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(timed // GRAPH_PLIES):
+            plies()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / timed
+        assert eng.error() == (0, -1)
+        eng.close()
+        del obs, eng
+        torch.cuda.empty_cache()
+        out[str(seed)] = dict(value=n / (ms / 1e3), ms_per_step=ms)
+    print(f"[bench] other seeds: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -549,6 +579,8 @@ def main():
     acting = None if args.no_history else acting_player_bench(E, torch, n)
     torch.cuda.empty_cache()
     search = None if args.no_history else search_bench(E, torch)
+    torch.cuda.empty_cache()
+    seeds = None if args.no_history else other_seeds_bench(E, torch, G, S, n)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -591,6 +623,7 @@ def main():
         "competitive_rules": two_square,
         "policies": policies,
         "search_shaped": search,
+        "other_seeds": seeds,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }
