@@ -37,8 +37,21 @@
  *                               from the rule's statement (App. A), including
  *                               Scout spans; the Scout case is a reading
  *   chasing rule .............. pinned by hand-built chases written from the
- *                               rule's statement and Table "chase"; threat,
- *                               evasion and the position window are readings
+ *                               rule's statement and Table "chase", and by a
+ *                               brute force that undoes the whole board
+ *                               history in chase-driven games; threat, evasion
+ *                               and the position window are readings
+ *   acting-player encoding .... pinned: equals the acting observer's half of
+ *                               the both-player encoding
+ *   magnet policy ............. pinned by closed forms (a lone Scout, two
+ *                               pieces) and by sampled piece and move
+ *                               frequencies (section 2.4, App. D.4)
+ *   search policy ............. pinned by optimality: it beats random points of
+ *                               the simplex on the regularised objective, and
+ *                               reduces to rho when q = 0 and pi_theta = rho
+ *                               (App. D.7)
+ *   policy sampler ............ pinned by sampled frequencies and by never
+ *                               drawing a zero-weight action
  */
 #include <stdint.h>
 #include <stdlib.h>
