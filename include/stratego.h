@@ -345,6 +345,21 @@ int stratego_history_info(stratego_ctx* ctx, int64_t t, const int32_t* games_dev
 int stratego_history_export(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
                             void* states_dev);
 
+/* BoardStrs of App. B (a debugging aid): a picture of each listed game's
+ * board at time step t (any step of the rollout buffer's window, as for the
+ * queries above).  Rows 9 down to 0, one text line each; per square three
+ * characters: the owner ('r' red, 'b' blue) and the type symbol (S Spy, 2
+ * Scout, 3 Miner, 4-9 Sergeant to General, M Marshal, F Flag, B Bomb), "~~"
+ * for a lake or ".." for an empty square, then a space (a newline after
+ * column 9).  out_host: host memory, count slots of
+ * STRATEGO_BOARD_STRING_BYTES bytes, each a NUL-terminated string.
+ * games_dev: int32[count] game indices (device memory) or NULL for games
+ * 0..count-1.  Synchronises the stream.  Errors: E_INVAL (an index outside
+ * [0, N), NULL out_host), E_RANGE, E_HIP. */
+#define STRATEGO_BOARD_STRING_BYTES 301
+int stratego_board_strings(stratego_ctx* ctx, int64_t t, const int32_t* games_dev, int32_t count,
+                           char* out_host);
+
 /* Policies over legal lists (sections 2.4-2.5 and App. D.7).  A game's legal list
  * is its acting player's legal actions in ascending order, padded to
  * STRATEGO_MAX_LEGAL entries with -1 (finished games: all -1).  Per-action

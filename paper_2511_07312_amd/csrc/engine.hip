@@ -1498,6 +1498,54 @@ int stratego_history_export(stratego_ctx* c, int64_t t, const int32_t* games, in
   return launch_hist(c, kQRecord, h);
 }
 
+// BoardStrs (App. B), a debugging aid: formatted on the host from the
+// records of time step t, copied out of the live states or the ring row.
+int stratego_board_strings(stratego_ctx* c, int64_t t, const int32_t* games, int32_t count, char* out) {
+  if (!c) return STRATEGO_E_INVAL;
+  HistArgs h;
+  int rc = hist_args(c, t, games, count, h);
+  if (rc != STRATEGO_OK || count == 0) return rc;
+  if (!out) return STRATEGO_E_INVAL;
+  const int N = c->cfg.num_games;
+  std::vector<int32_t> idx(count);
+  if (games) {
+    if (hipMemcpyAsync(idx.data(), games, sizeof(int32_t) * count, hipMemcpyDeviceToHost, c->stream) !=
+        hipSuccess)
+      return STRATEGO_E_HIP;
+  } else {
+    for (int32_t i = 0; i < count; ++i) idx[i] = i;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return STRATEGO_E_HIP;
+  for (int32_t i = 0; i < count; ++i)
+    if (idx[i] < 0 || idx[i] >= N) return STRATEGO_E_INVAL;
+  static const char kSymbol[12] = {'S', '2', '3', '4', '5', '6', '7', '8', '9', 'M', 'F', 'B'};
+  std::vector<uint8_t> rec(kRecordBytes);
+  for (int32_t i = 0; i < count; ++i) {
+    if (hipMemcpy(rec.data(), h.src + (size_t)idx[i] * kRecordBytes, kRecordBytes, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return STRATEGO_E_HIP;
+    char* o = out + (size_t)i * STRATEGO_BOARD_STRING_BYTES;
+    int k = 0;
+    for (int r = 9; r >= 0; --r) {
+      for (int col = 0; col < 10; ++col) {
+        const int v = (int8_t)rec[kOffBoard + 10 * r + col];
+        if (v == kLake) { o[k++] = '~'; o[k++] = '~'; }
+        else if (v < 0 || v >= kPieces) { o[k++] = '.'; o[k++] = '.'; }
+        else {
+          uint32_t w0;
+          std::memcpy(&w0, rec.data() + kOffPieces + 16 * v, sizeof(w0));
+          const int type = (int)(w0 & 15u);
+          o[k++] = v < 40 ? 'r' : 'b';
+          o[k++] = type < 12 ? kSymbol[type] : '?';
+        }
+        o[k++] = col == 9 ? '\n' : ' ';
+      }
+    }
+    o[k] = 0;
+  }
+  return STRATEGO_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -38,7 +38,7 @@ FUNCTIONS = [
     "stratego_destroy", "stratego_strerror", "stratego_serve", "stratego_history_window",
     "stratego_history_legal_mask", "stratego_history_encode_obs", "stratego_history_info",
     "stratego_history_export", "stratego_legal_list", "stratego_magnet_policy",
-    "stratego_search_policy", "stratego_sample_policy",
+    "stratego_search_policy", "stratego_sample_policy", "stratego_board_strings",
 ]
 REQ_STEP = 0
 REQ_ROLLOUT = 1
@@ -138,6 +138,7 @@ def load_library(path=LIB_PATH):
     L.stratego_magnet_policy.argtypes = [P, P]
     L.stratego_search_policy.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, P]
     L.stratego_sample_policy.argtypes = [P, P, P]
+    L.stratego_board_strings.argtypes = [P, I64, P, I32, ctypes.c_char_p]
     L.stratego_strerror.argtypes = [ctypes.c_int]
     L.stratego_strerror.restype = ctypes.c_char_p
     for f in FUNCTIONS:
@@ -282,6 +283,22 @@ def stratego_history_export(ctx, t, states, games=None, count=None):
     _check(load_library().stratego_history_export(
         ctx, int(t), _ptr(games, torch.int32, m, "games"), m,
         _ptr(states, torch.uint8, m * RECORD_BYTES, "states")), "stratego_history_export")
+
+
+BOARD_STRING_BYTES = 301
+
+
+def stratego_board_strings(ctx, t, games=None, count=None):
+    """BoardStrs of App. B: a text picture of each listed game's board at t."""
+    m = _listed(games, count)
+    if m == 0:
+        return []
+    buf = ctypes.create_string_buffer(m * BOARD_STRING_BYTES)
+    _check(load_library().stratego_board_strings(ctx, int(t), _ptr(games, torch.int32, m, "games"), m, buf),
+           "stratego_board_strings")
+    raw = buf.raw
+    return [raw[i * BOARD_STRING_BYTES:(i + 1) * BOARD_STRING_BYTES].split(b"\0", 1)[0].decode()
+            for i in range(m)]
 
 
 def stratego_legal_list(ctx, actions, num_legal=None):
@@ -536,6 +553,10 @@ class Engine:
         out = torch.empty((m, RECORD_BYTES), dtype=torch.uint8, device=self.device)
         stratego_history_export(self.ctx, t, out, games, m)
         return out
+
+    def board_strs(self, t=None, games=None):
+        """BoardStrs: one text picture per game at time step t (default: now)."""
+        return stratego_board_strings(self.ctx, self.window()[1] if t is None else t, games, self._list(games))
 
     def close(self):
         if self.ctx is not None:

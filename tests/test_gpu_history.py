@@ -238,3 +238,33 @@ def test_acting_player_views_at_past_steps():
             assert torch.equal(got, live[t])
     assert eng.error() == (0, -1)
     eng.close()
+
+
+def test_board_strings_match_the_oracle():
+    """BoardStrs (App. B): the library's text pictures at every step of the
+    window and for all games now equal the oracle's; errors for a step
+    outside the window and an index outside the games."""
+    n, seed, H = 50, 4, 3
+    kw = dict(k_battleless=20, max_moves=100, auto_reset=True)
+    eng = E.Engine(n, seed, history_len=H, **kw)
+    ref = O.OracleEngine(n, seed, **kw)
+    buf = O.OracleRolloutBuffer(ref, H)
+    for _ in range(5):
+        E.stratego_run_plies(eng.ctx, 1)
+        buf.ply(obs=False, mask=False)
+    lo, T = eng.window()
+    games = [0, 49, 7, 7]
+    g_dev = torch.tensor(games, dtype=torch.int32, device="cuda")
+    for t in range(lo, T + 1):
+        at = O.OracleEngine.from_records(buf.records_at(t, games), seed, **kw)
+        assert eng.board_strs(t, g_dev) == [at.board_string(i) for i in range(len(games))], t
+    now = eng.board_strs()
+    assert now == [ref.board_string(g) for g in range(n)]
+    assert all(len(s.splitlines()) == 10 for s in now)
+    with pytest.raises(E.StrategoError) as err:
+        eng.board_strs(lo - 1)
+    assert err.value.code == E.E_RANGE
+    with pytest.raises(E.StrategoError) as err:
+        eng.board_strs(T, torch.tensor([3, n], dtype=torch.int32, device="cuda"))
+    assert err.value.code == E.E_INVAL
+    eng.close()
