@@ -40,8 +40,8 @@
  *     The caller owns all buffers it passes; the library owns the game states
  *     (allocated once in stratego_init).
  *   - Every call is asynchronous on the HIP stream given at init, except
- *     stratego_get_error, stratego_autotune and stratego_destroy, which
- *     synchronise it.
+ *     stratego_get_error, stratego_autotune, stratego_serve,
+ *     stratego_board_strings and stratego_destroy, which synchronise it.
  *   - Return value: STRATEGO_OK (0) or a negative error code.  No C++
  *     exception crosses this interface.
  */
