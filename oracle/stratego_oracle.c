@@ -23,16 +23,23 @@
  * than itself):
  *   battle outcome ............ pinned: full 10x12 table fixture from Table pieces
  *   legal moves ............... pinned: brute-force pairwise predicate, closed form at ply 0
- *   setup shuffle ............. pinned: multiset/row invariants, uniformity test
+ *   setup shuffle ............. pinned: multiset/row invariants, uniformity test, and the
+ *                               Durstenfeld convention recomputed for 1000 game ids
  *   Philox4x32-10 ............. pinned: SC'11 known-answer vectors + an independent library
+ *   move samplers ............. pinned: the uniform (word x) and magnet (words y, z)
+ *                               conventions recomputed for 1000 games x 24 plies
  *   terminal logic ............ pinned: hand-built positions for every reason
  *   probability channels ...... pinned: brute-force enumeration of consistent assignments
+ *                               (known Scouts included), hand-built closed forms
  *   history features .......... parity unpinned by the paper (no worked example);
  *                               checked only by hand-built scenarios derived from
  *                               the written readings, plus invariants
- *   encoding layout ........... pinned by invariants and hand-built positions
- *   resampler ................. pinned by invariants and by agreement of its
- *                               empirical frequencies with the probability channels
+ *   encoding layout ........... pinned: every channel group against planes written
+ *                               by hand from the App. C.1 / C.2 tables (both frames,
+ *                               move planes most recent first), plus invariants
+ *   resampler ................. pinned by invariants, by agreement of its empirical
+ *                               frequencies with the probability channels, and by
+ *                               its convention recomputed for 1024 resamples
  *   two-square rule ........... pinned by hand-built move sequences written
  *                               from the rule's statement (App. A), including
  *                               Scout spans; the Scout case is a reading
@@ -108,6 +115,7 @@ typedef struct {
     int alive;
     int revealed;
     int moved;
+    int long_move;      /* once moved more than one square in one move (only a Scout can) */
     int death_square;   /* -1 while alive */
     int death_cause;    /* 0 while alive, else 1..6 (App. C.1 "Causes of death") */
     /* "has ever" sets (App. C.1): 11-bit sets, bit i < 10 = revealed type i,
@@ -327,8 +335,12 @@ static int chase_forbids(const orc_state* st, int player, int from, int to);
  * threats by one player and evasions by the other.  The chasing player may
  * not make a threat that recreates a position of the chase, unless the moved
  * piece returns to the square it held before that player's previous turn.
- * The positions of the chase are rebuilt here by undoing the moves of the
- * move record (its last 32 plies) on a copy of the board. */
+ * A position is the board together with the side to move, so the position a
+ * threat creates (the opponent to move) can only equal one an odd number of
+ * plies back.  The positions of the chase are rebuilt here by undoing the
+ * moves of the move record on a copy of the board; the record keeps the
+ * last 32 plies, so a chase is compared over at most that window. */
+#define CHASE_WINDOW RING
 static int threatens_after(const int board[NSQ], int sq, int player) {
     int nb[4], nn = neighbours(sq, nb);
     for (int i = 0; i < nn; i++) {
@@ -351,13 +363,13 @@ static int chase_forbids(const orc_state* st, int player, int from, int to) {
     if (st->ring_to[prev] == from && st->ring_from[prev] == to) return 0;
     int b[NSQ];
     memcpy(b, st->board, sizeof(b));
-    int K = L < st->ring_count ? L : st->ring_count;
+    int K = L < st->ring_count ? L : st->ring_count;           /* ring_count <= CHASE_WINDOW */
     for (int k = 1; k <= K; k++) {                             /* positions P_{L-1}, ..., P_{L-K} */
         int slot = (st->ply - k) & (RING - 1);
         int f = st->ring_from[slot], g = st->ring_to[slot];
         b[f] = b[g];
         b[g] = EMPTY;
-        if (memcmp(b, after, sizeof(b)) == 0) return 1;
+        if ((k & 1) && memcmp(b, after, sizeof(b)) == 0) return 1;   /* same side to move */
     }
     return 0;
 }
@@ -616,6 +628,8 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
         }
     }
     st->piece[X].moved = 1;
+    /* a move of more than one square is public proof of a Scout (App. A) */
+    if (!adjacent(from, to)) st->piece[X].long_move = 1;
 
     /* 5. threats made by the move: the mover, if it stands on `to`, against
      *    every adjacent enemy piece */
@@ -675,8 +689,11 @@ static int apply_action(orc_state* st, const orc_cfg* cfg, int action) {
 /* ------------------------------------------------------------------ */
 /* Probability channels (App. C.1 channels 12-35): the chance that a hidden
  * piece of player w has type T when the hidden types are a uniformly random
- * assignment of w's remaining type multiset, constrained only by "a piece
- * that has moved is neither Flag nor Bomb".  Returned as an exact rational. */
+ * assignment of w's remaining type multiset, constrained by every hard public
+ * fact: a piece that has moved is neither Flag nor Bomb, and a piece seen
+ * moving more than one square in one move is a Scout (App. A).  Such a piece
+ * is a known Scout: it leaves the hidden set and the multiset.  Returned as
+ * an exact rational for the pieces that stay unknown. */
 typedef struct {
     int n[NUM_TYPES];   /* hidden multiset */
     int H, I, M, U;
@@ -687,8 +704,8 @@ static void compute_hidden_stats(const orc_state* st, int w, hidden_stats* hs) {
     for (int t = 0; t < NUM_TYPES; t++) hs->n[t] = INITIAL_COUNT[t];
     for (int id = w * 40; id < w * 40 + 40; id++) {
         const orc_piece* p = &st->piece[id];
-        if (!p->alive || p->revealed) {
-            hs->n[p->type]--;           /* known type: revealed or dead */
+        if (!p->alive || p->revealed || p->long_move) {
+            hs->n[p->type]--;           /* known type: revealed, dead, or a known Scout */
         } else {
             hs->H++;
             if (p->moved) hs->M++;
@@ -770,8 +787,8 @@ static void encode(const orc_state* st, const orc_cfg* cfg, int o, uint8_t* out)
          * the opponent's point of view) */
         int pbase = own ? 24 : 12;
         const hidden_stats* hs = own ? &hs_own : &hs_opp;
-        if (P->revealed) {
-            put(out, pbase + P->type, f, 255);
+        if (P->revealed || P->long_move) {
+            put(out, pbase + P->type, f, 255);                      /* known type */
         } else {
             for (int t = 0; t < NUM_TYPES; t++) {
                 long num, den;
@@ -878,7 +895,7 @@ static void to_record(const orc_state* st, uint8_t* rec) {
                       ((uint32_t)p->revealed << 5) | ((uint32_t)p->moved << 6) |
                       ((uint32_t)p->death_cause << 7) |
                       ((uint32_t)(p->alive ? 127 : p->death_square) << 10) |
-                      ((uint32_t)p->been_against << 17);
+                      ((uint32_t)p->been_against << 17) | ((uint32_t)p->long_move << 30);
         uint32_t w1 = p->threat | (p->evade << 11);
         uint32_t w2 = p->adj | (p->prot << 11);
         uint32_t w3 = p->prot_against | (p->been_by << 13);
@@ -927,6 +944,7 @@ static void from_record(orc_state* st, const uint8_t* rec) {
         int dsq = (int)((w0 >> 10) & 127);
         p->death_square = p->alive ? -1 : dsq;
         p->been_against = (w0 >> 17) & 0x1FFF;
+        p->long_move = (int)((w0 >> 30) & 1);
         p->threat = w1 & 0x7FF;
         p->evade = (w1 >> 11) & 0x7FF;
         p->adj = w2 & 0x7FF;
@@ -939,7 +957,8 @@ static void from_record(orc_state* st, const uint8_t* rec) {
 /* ------------------------------------------------------------------ */
 /* Search-shaped resampling: draw the hidden types of player z uniformly
  * among assignments consistent with public information (revealed and dead
- * pieces known; a piece that moved is neither Flag nor Bomb).  Stands in
+ * pieces known; a piece seen moving more than one square is a Scout; a piece
+ * that moved is neither Flag nor Bomb).  Stands in
  * for the belief-model samples that search materialises on device (paper
  * section 2.5 and App. B reset behaviour). */
 static void resample(const orc_state* src, orc_state* dst, uint64_t seed, uint32_t new_game_id) {
@@ -980,7 +999,7 @@ static void resample(const orc_state* src, orc_state* dst, uint64_t seed, uint32
     int k = 0;
     for (int id = z * 40; id < z * 40 + 40; id++) {
         const orc_piece* p = &src->piece[id];
-        if (!p->alive || p->revealed) continue;
+        if (!p->alive || p->revealed || p->long_move) continue;
         if (assigned[id] >= 0) continue;
         assigned[id] = list[k++];
     }

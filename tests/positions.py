@@ -13,7 +13,8 @@ Record layout (little-endian):
   164..227 u8 ring[32][2] (from, to); the move made at ply t sits in slot t mod 32
   256 + 16*id: u32 w0, w1, w2, w3 per piece id (0..39 red, 40..79 blue)
     w0: type 0-3 | alive 4 | revealed 5 | moved 6 | death cause 7-9 |
-        death square 10-16 (127 while alive) | been-protected-against 17-29
+        death square 10-16 (127 while alive) | been-protected-against 17-29 |
+        long move 30 (the piece once moved more than one square)
     w1: threat 0-10 | evade 11-21
     w2: active adjacency 0-10 | protected 11-23
     w3: protected-against 0-12 | been-protected-by 13-25
@@ -43,12 +44,16 @@ def sq(row, col):
 
 
 def make_record(pieces, ply=0, battleless=0, game_id=0, episode=0, moves=(), done=0,
-                outcome=0, reason=0, dead_cause=6, dead_square=None, two_square=(None, None)):
+                outcome=0, reason=0, dead_cause=6, dead_square=None, two_square=(None, None),
+                dead=()):
     """pieces: list of dicts with keys sq, owner, type (name or index) and optional
-    revealed, moved, id, threat, evade, adj, prot, prot_against, been_by,
+    revealed, moved, long_move, id, threat, evade, adj, prot, prot_against, been_by,
     been_against.  Piece ids are taken from the owner's unused ids whose default
-    type matches, unless `id` is given.  Unplaced ids become dead pieces (revealed,
-    death square = their start square unless dead_square is given).
+    type matches, unless `id` is given.
+    dead: list of dicts with keys id, cause, sq (death square) and optional type
+    (default: the id's default type): pieces captured with that cause on that square.
+    Ids neither placed nor listed in `dead` become dead pieces too (revealed, death
+    square = their start square unless dead_square is given, cause dead_cause).
     moves: list of (from, to), oldest first; stored as the last len(moves) plies
     before `ply`.
     two_square: per player None or a list of squares (oldest first) occupied by
@@ -80,11 +85,20 @@ def make_record(pieces, ply=0, battleless=0, game_id=0, episode=0, moves=(), don
         board[s] = pid
         w0 = t | (1 << 4) | (int(p.get("revealed", 0)) << 5) | (int(p.get("moved", 0)) << 6)
         w0 |= 127 << 10
+        w0 |= int(p.get("long_move", 0)) << 30
         w0 |= int(p.get("been_against", 0)) << 17
         w1 = int(p.get("threat", 0)) | (int(p.get("evade", 0)) << 11)
         w2 = int(p.get("adj", 0)) | (int(p.get("prot", 0)) << 11)
         w3 = int(p.get("prot_against", 0)) | (int(p.get("been_by", 0)) << 13)
         words[pid] = (w0, w1, w2, w3)
+    # explicitly captured pieces
+    for d in dead:
+        pid = d["id"]
+        assert pid not in used
+        used.add(pid)
+        t = d.get("type", DEFAULT_TYPE[pid % 40])
+        t = t if isinstance(t, int) else T[t]
+        words[pid] = (t | (1 << 5) | (int(d["cause"]) << 7) | (int(d["sq"]) << 10), 0, 0, 0)
     # remaining ids are dead, with their default type unless already taken
     for owner in (0, 1):
         free_types = list(DEFAULT_TYPE)
@@ -140,8 +154,8 @@ def unpack_pieces(rec):
         out.append(dict(
             id=pid, type=w0 & 15, alive=(w0 >> 4) & 1, revealed=(w0 >> 5) & 1,
             moved=(w0 >> 6) & 1, death_cause=(w0 >> 7) & 7, death_square=(w0 >> 10) & 127,
-            been_against=(w0 >> 17) & 0x1FFF, threat=w1 & 0x7FF, evade=(w1 >> 11) & 0x7FF,
-            adj=w2 & 0x7FF, prot=(w2 >> 11) & 0x1FFF, prot_against=w3 & 0x1FFF,
+            been_against=(w0 >> 17) & 0x1FFF, long_move=(w0 >> 30) & 1,
+            threat=w1 & 0x7FF, evade=(w1 >> 11) & 0x7FF, adj=w2 & 0x7FF, prot=(w2 >> 11) & 0x1FFF, prot_against=w3 & 0x1FFF,
             been_by=(w3 >> 13) & 0x1FFF))
     return out
 

@@ -237,6 +237,28 @@ def test_lone_scout_has_18_moves():
         assert n == 18
 
 
+def test_long_moves_mark_a_known_scout():
+    # App. A: only a Scout moves more than one square; such a move is public
+    rec = make_record([dict(sq=sq(1, 0), owner=0, type="Scout"), dict(sq=sq(1, 9), owner=0, type="Scout"),
+                       dict(sq=sq(8, 0), owner=1, type="Scout"), dict(sq=sq(0, 0), owner=0, type="Flag"),
+                       dict(sq=sq(9, 9), owner=1, type="Flag")])
+    e = engine_from([rec])
+    far, near = int(board(rec)[10]), int(board(rec)[19])
+    _step(e, 100 * 10 + 40)          # (1,0) -> (4,0): three squares
+    _step(e, 100 * 80 + 70)          # blue one square
+    _step(e, 100 * 19 + 29)          # (1,9) -> (2,9): one square
+    pcs = unpack_pieces(e.export()[0])
+    assert pcs[far]["long_move"] == 1 and pcs[far]["moved"] == 1 and pcs[far]["revealed"] == 0
+    assert pcs[near]["long_move"] == 0 and pcs[near]["moved"] == 1
+    blue = int(board(rec)[80])
+    assert pcs[blue]["long_move"] == 0
+
+
+def _step(e, action):
+    r = e.step(np.array([action], dtype=np.int16))
+    assert r["first_bad"] == -1, action
+
+
 def test_scout_blocked_by_lake_piece_and_range_attack():
     # Scout at (4,0): east is blocked after (4,1) by the lake at (4,2)
     rec = make_record([dict(sq=sq(4, 0), owner=0, type="Scout"),
@@ -471,13 +493,18 @@ def test_probability_channels_at_ply0():
             assert PROB_PLY0 == [math.floor(255 * c / 40 + 0.5) for c in COUNTS]
 
 
-def enumerate_marginals(types, moved):
-    """Exact marginals by enumerating every distinct assignment of the hidden
-    multiset to the hidden pieces that gives no moved piece a Flag or Bomb."""
+def enumerate_marginals(types, moved, long_move=None):
+    """Exact marginals by enumerating every distinct assignment of the unknown
+    types to the unrevealed pieces that gives no moved piece a Flag or Bomb and
+    every piece seen moving more than one square the Scout type (App. A: only
+    Scouts move further than one square)."""
+    long_move = long_move or [0] * len(types)
     tally = [Counter() for _ in types]
     total = 0
     for perm in set(itertools.permutations(types)):
         if any(m and t in (FLAG, BOMB) for t, m in zip(perm, moved)):
+            continue
+        if any(lm and t != SCOUT for t, lm in zip(perm, long_move)):
             continue
         total += 1
         for i, t in enumerate(perm):
@@ -487,14 +514,16 @@ def enumerate_marginals(types, moved):
 
 def test_probability_channels_brute_force_enumeration():
     rng = np.random.default_rng(4)
-    for trial in range(40):
+    for trial in range(60):
         h = int(rng.integers(2, 8))
         pool = [t for t in range(12) for _ in range(COUNTS[t])]
         types = [int(x) for x in rng.choice(pool, size=h, replace=False)]
         moved = [int(t not in (FLAG, BOMB) and rng.integers(0, 2)) for t in types]
+        # some moved Scouts were seen moving more than one square
+        long_move = [int(m and t == SCOUT and rng.integers(0, 2)) for t, m in zip(types, moved)]
         squares = rng.choice([s for s in range(60, 100)], size=h, replace=False)
-        pieces = [dict(sq=int(s), owner=1, type=t, moved=m)
-                  for s, t, m in zip(squares, types, moved)]
+        pieces = [dict(sq=int(s), owner=1, type=t, moved=m, long_move=lm)
+                  for s, t, m, lm in zip(squares, types, moved, long_move)]
         pieces += [dict(sq=sq(0, 0), owner=0, type="Flag"),
                    dict(sq=sq(0, 1), owner=0, type="Scout", revealed=1)]
         # a few revealed blue pieces that must not disturb the hidden multiset
@@ -502,13 +531,16 @@ def test_probability_channels_brute_force_enumeration():
             pieces.append(dict(sq=sq(4, 5), owner=1, type="Miner", revealed=1))
         rec = make_record(pieces)
         e = engine_from([rec])
-        marg = enumerate_marginals(types, moved)
+        marg = enumerate_marginals(types, moved, long_move)
         x = e.encode()[0, 0].reshape(488, 100)       # red observes blue
         y = e.encode()[0, 1].reshape(488, 100)       # blue observes its own pieces via 24-35
         for i, s in enumerate(squares):
             for t in range(12):
-                num, den = O.hidden_prob(e, 0, 1, moved[i], t)
-                p = Fraction(num, den) if den else Fraction(0)
+                if long_move[i]:
+                    p = Fraction(int(t == SCOUT))     # a known Scout
+                else:
+                    num, den = O.hidden_prob(e, 0, 1, moved[i], t)
+                    p = Fraction(num, den) if den else Fraction(0)
                 assert p == marg[i][t]
                 q = math.floor(255 * p + Fraction(1, 2))
                 assert x[12 + t, int(s)] == q
@@ -549,7 +581,7 @@ def test_encoding_invariants_during_play():
                     # probability rows: each hidden square's exact probabilities sum to 1
                     for s in range(100):
                         pid = b[s]
-                        if pid < 0 or pcs[pid]["revealed"]:
+                        if pid < 0 or pcs[pid]["revealed"] or pcs[pid]["long_move"]:
                             continue
                         w = pid // 40
                         tot = Fraction(0)
@@ -632,7 +664,7 @@ def test_resample_invariants_and_observer_obs_unchanged():
             pr = unpack_pieces(out[k])
             assert Counter(p["type"] for p in pr[40:]) == Counter(p["type"] for p in ps[40:])
             for pid in range(80):
-                if pid < 40 or ps[pid]["revealed"] or not ps[pid]["alive"]:
+                if pid < 40 or ps[pid]["revealed"] or not ps[pid]["alive"] or ps[pid]["long_move"]:
                     assert pr[pid]["type"] == ps[pid]["type"]
                 if pr[pid]["moved"] and pr[pid]["alive"]:
                     assert pr[pid]["type"] not in (FLAG, BOMB)
@@ -654,8 +686,11 @@ def test_resample_frequencies_match_probability_channels():
     types = np.array([[int(out[k][256 + 16 * pid]) & 15 for pid in hidden] for k in range(per)])
     for col, pid in enumerate(hidden[:12]):
         for t in range(12):
-            num, den = O.hidden_prob(src, 0, 1, ps[pid]["moved"], t)
-            p = num / den if den else 0.0
+            if ps[pid]["long_move"]:
+                p = float(t == SCOUT)                 # a known Scout keeps its type
+            else:
+                num, den = O.hidden_prob(src, 0, 1, ps[pid]["moved"], t)
+                p = num / den if den else 0.0
             f = (types[:, col] == t).mean()
             assert abs(f - p) < 5 * math.sqrt(max(p * (1 - p), 1e-9) / per) + 1e-9, (pid, t, f, p)
 
@@ -917,6 +952,52 @@ def test_chasing_rule_forbids_a_repeated_position():
     assert 12 not in _moves_of(again, 2)
 
 
+def test_chasing_rule_compares_positions_with_the_same_side_to_move():
+    # A red Scout circles 20 -> 22 -> 21 while a blue Lieutenant steps 32 -> 31
+    # -> 32 away from it; a blue Bomb on 30 keeps 20 a threat square.  Each red
+    # move is a threat and each blue move an evasion, so after four plies the
+    # chase has length 4 and red is to move.  The threat 21 -> 20 recreates the
+    # board of the chase's start, but there red was to move and after the
+    # threat blue is: not the same position, so the move stays legal.
+    def position():
+        return make_record([dict(sq=20, owner=0, type="Scout"), dict(sq=32, owner=1, type="Lieutenant"),
+                            dict(sq=30, owner=1, type="Bomb"), dict(sq=sq(7, 9), owner=0, type="Flag"),
+                            dict(sq=sq(9, 0), owner=1, type="Flag")])
+    on = engine_from([position()], chasing=True, k_battleless=1000)
+    _play(on, [2022, 3231, 2221, 3132])
+    assert int(on.export()[0][40]) == 4 and int(on.export()[0][41]) == 0
+    assert 20 in _moves_of(on, 21)
+    b0 = [int(v) for v in board(position())]
+    res = [int(v) for v in board(on.export()[0])]
+    res[20], res[21] = res[21], -1
+    assert res == b0                      # the board would indeed repeat
+
+
+def _loop(cols):
+    """The border of rows 0-3 x cols 0..cols-1, in walking order."""
+    return ([sq(0, c) for c in range(cols)] + [sq(r, cols - 1) for r in (1, 2, 3)] +
+            [sq(3, c) for c in range(cols - 2, -1, -1)] + [sq(r, 0) for r in (2, 1)])
+
+
+@pytest.mark.parametrize("cols,forbidden", [(6, True), (7, False)])
+def test_chasing_rule_window_is_the_32_ply_move_record(cols, forbidden):
+    # A red Captain follows a blue Lieutenant around a loop of squares, one step
+    # behind it: every red move threatens, every blue move evades, so the chase
+    # grows by one each ply.  Around a 16-square loop (cols 0-5) the position
+    # after red's first threat comes back 31 plies later, inside the 32 plies
+    # the move record keeps: forbidden.  Around an 18-square loop (cols 0-6) it
+    # comes back after 35 plies, beyond the record: the rule does not see it.
+    loop = _loop(cols)
+    n = len(loop)
+    rec = make_record([dict(sq=loop[0], owner=0, type="Captain"), dict(sq=loop[2], owner=1, type="Lieutenant"),
+                       dict(sq=sq(7, 9), owner=0, type="Flag"), dict(sq=sq(9, 0), owner=1, type="Flag")])
+    e = engine_from([rec], chasing=True, k_battleless=1000)
+    for i in range(n):
+        _play(e, [100 * loop[i] + loop[(i + 1) % n], 100 * loop[(i + 2) % n] + loop[(i + 3) % n]])
+    assert int(e.export()[0][40]) == 2 * n and int(e.export()[0][41]) == 0
+    assert (loop[1] not in _moves_of(e, loop[0])) == forbidden
+
+
 def test_chase_ends_on_a_battle_or_a_non_evasion():
     e = engine_from([_chase_position()], chasing=True)
     _play(e, _CHASE[:3])
@@ -1021,7 +1102,9 @@ def test_chasing_rule_against_full_board_history():
             got = set(np.flatnonzero(l_off & ~l_on).tolist())
             want = set()
             if L >= 2 and L % 2 == 0 and C == q:
-                window = hist[g][-1 - min(L, 32):-1]
+                # positions of the chase within the 32-ply record with the same
+                # side to move as the one a threat creates: an odd number of plies back
+                window = [hist[g][-1 - k] for k in range(1, min(L, 32) + 1) if k % 2 == 1]
                 prev = (int(after[g][8]) - 2) & 31
                 prev_f, prev_t = int(after[g][164 + 2 * prev]), int(after[g][165 + 2 * prev])
                 for act in np.flatnonzero(l_off):
