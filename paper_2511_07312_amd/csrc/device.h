@@ -165,11 +165,16 @@ __device__ __forceinline__ void set_hdr_u32(uint8_t* R, int off, uint32_t v) {
 }
 
 // w0 fields: type 0-3, alive 4, revealed 5, moved 6, death cause 7-9,
-// death square 10-16, been-protected-against 17-29
+// death square 10-16, been-protected-against 17-29, long move 30 (the piece
+// once moved more than one square: App. A lets only a Scout do that, so its
+// type is public although no battle revealed it)
 __device__ __forceinline__ int p_type(uint32_t w0) { return w0 & 15; }
 __device__ __forceinline__ bool p_alive(uint32_t w0) { return (w0 >> 4) & 1; }
 __device__ __forceinline__ bool p_revealed(uint32_t w0) { return (w0 >> 5) & 1; }
 __device__ __forceinline__ bool p_moved(uint32_t w0) { return (w0 >> 6) & 1; }
+__device__ __forceinline__ bool p_long(uint32_t w0) { return (w0 >> 30) & 1; }
+// the type is public: revealed in a battle, or a known Scout
+__device__ __forceinline__ bool p_known(uint32_t w0) { return (w0 & ((1u << 5) | (1u << 30))) != 0; }
 __device__ __forceinline__ int owner(int id) { return id >= 40 ? 1 : 0; }
 __device__ __forceinline__ int start_sq(int id) { return id < 40 ? id : 139 - id; }
 __device__ __forceinline__ bool movable_type(int t) { return t < kFlag; }
@@ -386,8 +391,8 @@ __device__ __forceinline__ void two_square_update(uint8_t* R, int p, int X, int 
 // one player and evasions by the other.  The chasing player may not make a
 // threat that recreates a position of the chase, unless the moved piece
 // returns to the square it held before that player's previous turn.  The
-// chase's positions (within the 32-ply move record) are compared with the
-// current one by their differences: undoing the chase's moves one by one,
+// chase's positions (within the 32-ply move record; a position includes the
+// side to move) are compared with the current one by their differences: undoing the chase's moves one by one,
 // a position that differs from the current one in a single piece of the
 // chaser, standing on square s, forbids that piece's move to s.
 // Work area (per wave, 160 bytes of LDS): displaced pieces, their current
@@ -428,7 +433,9 @@ __device__ __forceinline__ int chase_forbidden_list(const uint8_t* R, int p, uin
     ndiff -= at[e] != cur[e];
     at[e] = (uint8_t)f;
     ndiff += at[e] != cur[e];
-    if (ndiff != 1) continue;
+    // a threat leaves the opponent to move: only positions an odd number of
+    // plies back have the same side to move
+    if (ndiff != 1 || (k & 1) == 0) continue;
     int x = -1, sq = -1, id = -1;
     for (int i = 0; i < ne; ++i)
       if (at[i] != cur[i]) { x = cur[i]; sq = at[i]; id = pc[i]; }
@@ -924,6 +931,7 @@ __device__ __forceinline__ void apply_action(uint8_t* R, Rules rules, int action
       }
     }
     px[0] |= 1u << 6;   // moved
+    if (!adjacent(from, to)) px[0] |= 1u << 30;   // a long move: a known Scout
     // 5. threats by the mover from its destination
     if (attacker_alive) {
       for (int k = 0; k < 4; ++k) {
@@ -1020,10 +1028,12 @@ __device__ __forceinline__ StepOut step_game(uint8_t* R, uint8_t* scratch, uint8
 }
 
 // ---------------------------------------------------------------- probabilities
-// Channels 12-35 (App. C.1): chance that a hidden piece has type T when the
-// hidden types are a uniform assignment of the owner's remaining multiset in
-// which no moved piece is a Flag or Bomb.  With H hidden pieces, I hidden
-// Flag+Bomb, M moved hidden, U = H - M unmoved hidden and n_T remaining of T:
+// Channels 12-35 (App. C.1): chance that a piece of unknown type has type T
+// when the unknown types are a uniform assignment of the owner's remaining
+// multiset in which no moved piece is a Flag or Bomb.  Revealed pieces and
+// known Scouts (a move of more than one square, App. A) are out of the
+// multiset.  With H unknown pieces, I unknown Flag+Bomb, M moved unknown,
+// U = H - M unmoved unknown and n_T remaining of T:
 // moved: n_T/(H-I) for movable T, 0 otherwise; unmoved: n_T/U for Flag/Bomb,
 // n_T(U-I)/(U(H-I)) for movable T.  Stored as round-half-up(255 p) in
 // probq[owner][moved][type].
@@ -1042,7 +1052,7 @@ __device__ __forceinline__ void compute_probq(const uint8_t* R, uint8_t* slab) {
     if (id < kPieces) {
       uint32_t w0 = piece_words(R, id)[0];
       int w = owner(id);
-      if (!p_alive(w0) || p_revealed(w0)) {
+      if (!p_alive(w0) || p_known(w0)) {
         atomicAdd(&cnt[12 * w + p_type(w0)], 1);
       } else {
         atomicAdd(&cnt[24 + w], 1);
@@ -1120,7 +1130,7 @@ __device__ __forceinline__ void scatter_segment(const uint8_t* R, const uint8_t*
       W.put(w, t, fw, 1);                                  // 0-11 own type
       if (!rev) { W.put(w, 36, fw, 1); W.put(e, 37, fe, 1); }
       if (mv) { W.put(w, 39, fw, 1); W.put(e, 40, fe, 1); }
-      if (rev) {                                           // 12-35 known type
+      if (p_known(w0)) {                                   // 12-35 known type
         W.put(w, 24 + t, fw, 255);
         W.put(e, 12 + t, fe, 255);
       } else {                                             // 12-35 probabilities
@@ -1287,12 +1297,14 @@ __device__ __forceinline__ void build_bitplanes(const uint8_t* R, uint8_t* slab)
       const int t = p_type(w0);
       const bool rev = p_revealed(w0), mv = p_moved(w0);
       plane_set(slab, w, t, fw);
-      if (rev) {
+      if (!rev) {
+        plane_set(slab, w, 36, fw);
+        plane_set(slab, e, 37, fe);
+      }
+      if (p_known(w0)) {
         plane_set(slab, w, 24 + t, fw);
         plane_set(slab, e, 12 + t, fe);
       } else {
-        plane_set(slab, w, 36, fw);
-        plane_set(slab, e, 37, fe);
         const uint8_t own_cat = mv ? 3 : 4, opp_cat = mv ? 1 : 2;
         if (w == 0) { cat0 = own_cat; cat1 = opp_cat; } else { cat1 = own_cat; cat0 = opp_cat; }
       }
@@ -1442,11 +1454,9 @@ __device__ __forceinline__ void build_bitplanes1(const uint8_t* R, uint8_t* slab
       const int t = p_type(w0);
       const bool rev = p_revealed(w0), mv = p_moved(w0);
       if (own) set(t, f);
-      if (rev) set((own ? 24 : 12) + t, f);
-      else {
-        set(own ? 36 : 37, f);
-        cat = own ? (mv ? 3 : 4) : (mv ? 1 : 2);
-      }
+      if (!rev) set(own ? 36 : 37, f);
+      if (p_known(w0)) set((own ? 24 : 12) + t, f);
+      else cat = own ? (mv ? 3 : 4) : (mv ? 1 : 2);
       if (mv) set(own ? 39 : 40, f);
       uint32_t th = pw[1] & 0x7FFu, ev = (pw[1] >> 11) & 0x7FFu, ad = pw[2] & 0x7FFu;
       const int b_th = own ? 43 : 76, b_ev = own ? 54 : 87, b_ad = own ? 65 : 98;
@@ -1548,8 +1558,8 @@ __device__ __forceinline__ void encode_game(const uint8_t* R, uint8_t* slab, Rul
 // ---------------------------------------------------------------- resampling
 // Hidden types of the player not to move redrawn uniformly among assignments
 // consistent with public information (paper section 2.5; belief samples are
-// replaced by this uniform model): first the Flag and Bombs among the unmoved
-// hidden pieces (partial Fisher-Yates in ascending id order, Flag first), then
+// replaced by this uniform model; revealed pieces and known Scouts keep their
+// types): first the Flag and Bombs among the unmoved hidden pieces (partial Fisher-Yates in ascending id order, Flag first), then
 // the movable multiset shuffled over the remaining hidden pieces in ascending
 // id order.  The random words (Philox counter (new id, block, episode, 3),
 // words x, y, z, w of each block in turn) are drawn one per lane, the two
@@ -1568,7 +1578,7 @@ __device__ __forceinline__ int lane_swap(int v, int a, int b) {
 struct ResampleSource {
   int z, nu, I, L, nflag;
   uint32_t episode;
-  uint64_t hidden;   // bit m: piece 40 z + m is alive and unrevealed
+  uint64_t hidden;   // bit m: piece 40 z + m is alive and of unknown type
   int unmoved;       // lane m < nu: id of the m-th unmoved hidden piece of z, ascending
   int list;          // lane m < L: the m-th type of z's hidden movable multiset, sorted
   uint4 c0, c1;      // the record's 16-byte chunks lane and 64 + lane (lane < 32)
@@ -1581,8 +1591,8 @@ __device__ __forceinline__ ResampleSource resample_prepare(const uint8_t* R) {
   S.episode = hdr_u32(R, kOffEpisode);
   const bool mine = lane < 40;
   const uint32_t w0 = mine ? piece_words(R, 40 * S.z + lane)[0] : 0u;
-  const bool known = mine && (!p_alive(w0) || p_revealed(w0));
-  const bool hid = mine && p_alive(w0) && !p_revealed(w0);
+  const bool known = mine && (!p_alive(w0) || p_known(w0));
+  const bool hid = mine && p_alive(w0) && !p_known(w0);
   const int t = p_type(w0);
   S.hidden = ballot(hid);
   const uint64_t um = ballot(hid && !p_moved(w0));
@@ -1679,6 +1689,7 @@ __device__ __forceinline__ bool record_ok(const uint8_t* R) {
       my_type[h] = t;
       if (t > 11) bad = true;
       if (p_moved(w0) && !movable_type(t)) bad = true;
+      if (p_long(w0) && (!p_moved(w0) || t != kScout)) bad = true;
       const int cause = (w0 >> 7) & 7, dsq = (w0 >> 10) & 127;
       if (p_alive(w0)) {
         if (cause != 0 || dsq != 127) bad = true;
