@@ -33,9 +33,11 @@
  *     40 and u8 chasing player at 41; i8 board[100] at 64 (piece id, -1
  *     empty, -2 lake); u8 ring[32][2] of (from, to) at 164, the move of ply t
  *     in slot t mod 32; at 256 + 16 id four u32 words per piece id (0-39 red,
- *     40-79 blue): type, alive, revealed, moved, death cause and square, and
- *     the history-feature bits of App. C.1.  Records are the checkpoint
- *     format: importing an exported record continues the game bit-exactly.
+ *     40-79 blue): type, alive, revealed, moved, death cause and square, the
+ *     history-feature bits of App. C.1, and (word 0 bit 30) whether the piece
+ *     ever moved more than one square, which App. A allows only a Scout, so
+ *     that its type is public.  Records are the checkpoint format: importing
+ *     an exported record continues the game bit-exactly.
  *   - Every device pointer must be device memory on the context's device.
  *     The caller owns all buffers it passes; the library owns the game states
  *     (allocated once in stratego_init).
@@ -92,8 +94,9 @@ typedef struct {
                               piece with a legal move uniformly, then one of its moves) */
   int32_t chasing_rule;    /* 1: continuous-chasing rule (App. A, Table "chase", App. B.3): the
                               chasing player may not make a threat that recreates a position
-                              of the chase (within the last 32 plies), unless the moved piece
-                              returns to its square before that player's previous turn */
+                              of the chase (board and side to move, within the last 32 plies),
+                              unless the moved piece returns to its square before that
+                              player's previous turn */
   int32_t acting_obs_only; /* 1: every observation output holds only the acting player's
                               information state, uint8[N][1][488][10][10] (App. B.1
                               ComputeInfostateTensor); 0: both players, [N][2][488][10][10] */
@@ -111,7 +114,8 @@ int stratego_init(const stratego_config* cfg, void* hip_stream, stratego_ctx** o
  * records copied into the slots.  A malformed record (lakes not exactly on
  * the lake squares, a board entry out of range or naming a dead piece, an
  * alive piece not on exactly one square, a player's types not the initial
- * multiset, a moved Flag or Bomb, a dead piece unrevealed or with a bad death
+ * multiset, a moved Flag or Bomb, a long-move bit on a piece that is not a
+ * moved Scout, a dead piece unrevealed or with a bad death
  * cause or square, ring squares or counters out of range, malformed
  * two-square or chase state) or a slot outside [0, N) latches E_BAD_STATE in
  * the error word (see stratego_get_error) and leaves that slot unchanged. */
@@ -146,10 +150,17 @@ int stratego_step(stratego_ctx* ctx, const int16_t* actions_dev, int8_t* done_de
  * Errors: E_INVAL (NULL obs_dev). */
 int stratego_encode_obs(stratego_ctx* ctx, uint8_t* obs_dev);
 
-/* Copy the N canonical records (1536 bytes each) to states_dev (device). */
+/* Copy the N canonical records (1536 bytes each) to states_dev (device).  The
+ * records are the compact state the paper's simulator keeps per game, from
+ * which masks and information states are recomputed on demand (App. B, B.1);
+ * imported with stratego_reset they restore the games exactly (a checkpoint,
+ * or a snapshot of states for search). */
 int stratego_export_states(stratego_ctx* ctx, void* states_dev);
 
-/* Fused engine (one persistent kernel per ply): for each of nplies plies and
+/* Fused engine (one persistent kernel per ply): the step loop of the paper's
+ * data collection and rollouts (App. B: the simulator advances all games in
+ * lockstep; section 2.6, App. D.2: self-play generation), with the calls above
+ * fused.  For each of nplies plies and
  * every game, legal mask -> sample (the context's sampler) -> encode the
  * observations of the pre-move state (both players, or the acting player's
  * with acting_obs_only) -> step (with the context's auto-reset).  The per-ply
@@ -183,7 +194,8 @@ int stratego_run_plies_slots(stratego_ctx* ctx, const int32_t* slots_dev, int32_
  * consistent with public information (revealed and dead pieces keep their
  * types; a piece that has moved is neither Flag nor Bomb), drawn from
  * Philox4x32-10(key = seed, counter = (new id, block, episode, 3)); the new
- * game id is game_id_base + i*per + j; slots from nsrc*per on are left as
+ * game id is game_id_base + i*per + j; a piece seen moving more than one
+ * square keeps its type (a known Scout); slots from nsrc*per on are left as
  * they are.  A malformed source record latches E_BAD_STATE with the slot of
  * its first resample (i*per) and its slots are left as they are.  Errors:
  * E_INVAL (null source, nsrc or per below 1, nsrc*per above N), E_HIP. */

@@ -718,18 +718,23 @@ bool valid_tiling(int G, int L) {
   return (G == 1 || G == 2 || G == 4 || G == 8 || G == 16) && valid_layout(L);
 }
 
+// What a launch needs to know of its device.
+struct DevLimits {
+  int num_cu;
+  size_t max_lds;   // dynamic LDS one workgroup may use
+};
+
 // Waves per workgroup: four when their LDS fits, else two, else one; each wave
 // takes its own chunks of G games.
-size_t g_max_lds = 65536;
-inline int waves_for(int G, int S) {
+inline int waves_for(int G, int S, size_t max_lds) {
   (void)G;
   for (int w = 4; w > 1; w >>= 1)
-    if ((size_t)w * wave_lds_bytes(S) <= g_max_lds) return w;
+    if ((size_t)w * wave_lds_bytes(S) <= max_lds) return w;
   return 1;
 }
 
 // Dynamic LDS of one fused-engine workgroup.
-inline size_t lds_for(int G, int S) { return (size_t)waves_for(G, S) * wave_lds_bytes(S); }
+inline size_t lds_for(int G, int S, size_t max_lds) { return (size_t)waves_for(G, S, max_lds) * wave_lds_bytes(S); }
 
 const void* fused_kernel(int enc) {
   return enc == 1 ? reinterpret_cast<const void*>(&k_ply<kFused, 1>)
@@ -741,15 +746,15 @@ const void* fused_kernel(int enc) {
 // grow: observation-free plies, where a game is short next to the loop's
 // fixed costs; the tile grows up to 8 games while every wave still gets two
 // or more.
-int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent,
+int launch_ply(const DevLimits& d, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent,
                bool grow = false) {
   // fused plies without observations take the observation-free variant,
   // whatever staging layout the encoder is tuned to
   const bool no_obs = mode == kFused && a.obs == nullptr;
   const int enc = no_obs ? kEncNone : S == kLayoutBits ? 1 : S == kLayoutBits1 ? 2 : 0;
-  const int W = no_obs ? 4 : (mode == kFused) ? waves_for(G, S) : 4;
+  const int W = no_obs ? 4 : (mode == kFused) ? waves_for(G, S, d.max_lds) : 4;
   const size_t lds = (size_t)W * ply_wave_lds_bytes(enc, S);
-  if (lds > c->max_lds) return STRATEGO_E_INVAL;
+  if (lds > d.max_lds) return STRATEGO_E_INVAL;
   const void* fn = nullptr;
   switch (mode) {
     case kFused:
@@ -771,7 +776,7 @@ int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * W, lds) != hipSuccess || per_cu <= 0)
       return STRATEGO_E_INVAL;
-    cap = per_cu * c->num_cu;
+    cap = per_cu * d.num_cu;
   }
   int tile = (mode == kFused) ? G : 1;
   if (persistent && grow) {
@@ -786,6 +791,13 @@ int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S
   void* args[] = {&a};
   if (hipLaunchKernel(fn, dim3(grid), dim3(64 * W), args, lds, s) != hipSuccess) return STRATEGO_E_HIP;
   return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
+}
+
+inline DevLimits limits_of(const stratego_ctx* c) { return DevLimits{c->num_cu, c->max_lds}; }
+
+int launch_ply(stratego_ctx* c, hipStream_t s, int mode, PlyArgs a, int G, int S, bool persistent,
+               bool grow = false) {
+  return launch_ply(limits_of(c), s, mode, a, G, S, persistent, grow);
 }
 
 PlyArgs base_args(stratego_ctx* c) {
@@ -909,8 +921,7 @@ static int init_context(const stratego_config* cfg, void* hip_stream, stratego_c
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; return STRATEGO_E_HIP; }
   c->num_cu = prop.multiProcessorCount;
   c->max_lds = prop.sharedMemPerBlock;
-  g_max_lds = c->max_lds;
-  if (lds_for(G, S) > c->max_lds) { delete c; return STRATEGO_E_INVAL; }
+  if (lds_for(G, S, c->max_lds) > c->max_lds) { delete c; return STRATEGO_E_INVAL; }
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0)
     khz = 100000;
@@ -1333,7 +1344,7 @@ int stratego_get_tiling(stratego_ctx* c, int32_t* G, int32_t* S) {
 }
 
 int stratego_set_tiling(stratego_ctx* c, int32_t G, int32_t S) {
-  if (!c || !valid_tiling(G, S) || lds_for(G, S) > c->max_lds) return STRATEGO_E_INVAL;
+  if (!c || !valid_tiling(G, S) || lds_for(G, S, c->max_lds) > c->max_lds) return STRATEGO_E_INVAL;
   c->G = G;
   c->S = S;
   return STRATEGO_OK;
@@ -1360,10 +1371,11 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
   for (int gi = 0; gi < 5 && rc == STRATEGO_OK; ++gi) {
     for (int si = 0; si < 7 && rc == STRATEGO_OK; ++si) {
       const int G = Gs[gi], S = Ss[si];
-      if (lds_for(G, S) > c->max_lds) continue;
+      const size_t lds = lds_for(G, S, c->max_lds);
+      if (lds > c->max_lds) continue;
       int per_cu = 0;
       const void* fused = fused_kernel(S == kLayoutBits ? 1 : S == kLayoutBits1 ? 2 : 0);
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64 * waves_for(G, S), lds_for(G, S)) !=
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64 * waves_for(G, S, c->max_lds), lds) !=
               hipSuccess ||
           per_cu <= 0)
         continue;
