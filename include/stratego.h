@@ -177,6 +177,34 @@ int stratego_run_plies(stratego_ctx* ctx, int32_t nplies, uint64_t* mask_dev,
                        int8_t* done_dev, int8_t* outcome_dev, uint8_t* reason_dev,
                        int16_t* ep_len_dev, int32_t use_graph, int64_t* ply_ns_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc): stratego_run_plies
+ * without a context or a graph, over caller-owned records.  states_dev:
+ * uint8[cfg->num_games][1536] canonical records as the library writes them
+ * (stratego_export_states, stratego_history_export, or an earlier call of
+ * this function), advanced in place; slot i is game i.  cfg gives the rules,
+ * the sampler, the observation mode and the tiling as for stratego_init
+ * (num_games, k_battleless, max_moves, auto_reset, seed, two_square_rule,
+ * sampler, chasing_rule, acting_obs_only, games_per_wg, lds_layout);
+ * game_id_base is not used (records carry their game ids) and history_len
+ * must be 0.  Outputs as for stratego_run_plies, any may be NULL.  The call
+ * allocates nothing: the per-ply work counters of the persistent kernel sit
+ * in a static device array of STRATEGO_STATIC_MAX_PLIES counters that each
+ * device holds for the life of the process and that every call on that
+ * device reuses (the first call on a device also looks up that array's
+ * address and the device's limits).  Calls that overlap on one device
+ * (different streams, or different host threads without ordering) race on
+ * the counters and must not be made.  Asynchronous on hip_stream (NULL = the
+ * null stream), which must belong to the current device.  Drawn actions are
+ * legal by construction, so no error word is kept.  Errors: E_INVAL (NULL
+ * cfg or states_dev, an invalid cfg field, nplies outside [0,
+ * STRATEGO_STATIC_MAX_PLIES], more devices than the library tracks), E_HIP. */
+#define STRATEGO_STATIC_MAX_PLIES 4096
+int stratego_run_plies_static(const stratego_config* cfg, void* hip_stream, void* states_dev, int32_t nplies,
+                              uint64_t* mask_dev, int16_t* num_legal_dev, int16_t* actions_dev,
+                              uint8_t* obs_dev, int8_t* done_dev, int8_t* outcome_dev, uint8_t* reason_dev,
+                              int16_t* ep_len_dev);
+
 /* Same as stratego_run_plies over a subset of slots (serving): slots_dev
  * int32[nslots] (distinct, each in [0, N); an out-of-range entry is skipped
  * and latches E_BAD_STATE with its list position); per-game outputs are

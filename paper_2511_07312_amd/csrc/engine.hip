@@ -14,6 +14,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -1119,6 +1120,125 @@ int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t*
   }
   c->steps += (int64_t)nplies * n;
   c->t += nplies;
+  return STRATEGO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Fused plies over caller-owned records without allocation.  Their per-ply
+// work counters (and the error word the ply kernel expects) live in this
+// file-scope array, of which every device holds its own copy until the
+// process ends; calls that overlap on one device share it.  Host code uses
+// the per-device address obtained from hipGetSymbolAddress, never the
+// array's name.
+constexpr int kStaticMaxPlies = STRATEGO_STATIC_MAX_PLIES;
+constexpr int kStaticErr = kStaticMaxPlies;   // two int32 words after the counters
+
+}  // namespace
+
+static __device__ __align__(256) unsigned int scratch[kStaticMaxPlies + 64];
+
+namespace {
+
+struct StaticDevice {
+  std::once_flag once;
+  int rc;
+  DevLimits lim;
+  unsigned int* scratch;   // this device's copy of the array
+};
+constexpr int kMaxStaticDevices = 64;
+StaticDevice g_static[kMaxStaticDevices];
+
+// Once per device, with that device current: the array's address there, the
+// device's limits, and the LDS attribute of the kernels that need it.
+int static_device(StaticDevice** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return STRATEGO_E_HIP;
+  if (dev < 0 || dev >= kMaxStaticDevices) return STRATEGO_E_INVAL;
+  StaticDevice& d = g_static[dev];
+  std::call_once(d.once, [&]() {
+    d.rc = STRATEGO_OK;
+    d.scratch = nullptr;
+    void* ptr = nullptr;
+    hipDeviceProp_t prop;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr ||
+        hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      d.rc = STRATEGO_E_HIP;
+      return;
+    }
+    d.scratch = reinterpret_cast<unsigned int*>(ptr);
+    d.lim = DevLimits{prop.multiProcessorCount, prop.sharedMemPerBlock};
+    for (int enc = 0; enc < 3; ++enc)
+      (void)hipFuncSetAttribute(fused_kernel(enc), hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lim.max_lds);
+  });
+  *out = &d;
+  return d.rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stratego_run_plies_static(const stratego_config* cfg, void* hip_stream, void* states_dev, int32_t nplies,
+                              uint64_t* mask, int16_t* num_legal, int16_t* actions, uint8_t* obs, int8_t* done,
+                              int8_t* outcome, uint8_t* reason, int16_t* ep_len) {
+  if (!cfg || !states_dev || nplies < 0 || nplies > kStaticMaxPlies) return STRATEGO_E_INVAL;
+  if (cfg->num_games <= 0 || cfg->k_battleless <= 0 || cfg->max_moves <= 0 || cfg->max_moves > 32767 ||
+      (cfg->auto_reset != 0 && cfg->auto_reset != 1) ||
+      (cfg->two_square_rule != 0 && cfg->two_square_rule != 1) ||
+      (cfg->sampler != kSamplerUniform && cfg->sampler != kSamplerMagnet) ||
+      (cfg->chasing_rule != 0 && cfg->chasing_rule != 1) ||
+      (cfg->acting_obs_only != 0 && cfg->acting_obs_only != 1) || cfg->history_len != 0)
+    return STRATEGO_E_INVAL;
+  const int G = cfg->games_per_wg ? cfg->games_per_wg : 1;
+  const int S = cfg->lds_layout ? cfg->lds_layout : kLayoutBits;
+  if (!valid_tiling(G, S)) return STRATEGO_E_INVAL;
+  StaticDevice* d = nullptr;
+  int rc = static_device(&d);
+  if (rc != STRATEGO_OK) return rc;
+  if (lds_for(G, S, d->lim.max_lds) > d->lim.max_lds) return STRATEGO_E_INVAL;
+  if (nplies == 0) return STRATEGO_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const int n = cfg->num_games;
+  Rules rules;
+  rules.seed = cfg->seed;
+  rules.k_battleless = cfg->k_battleless;
+  rules.max_moves = cfg->max_moves;
+  rules.auto_reset = cfg->auto_reset;
+  rules.two_square = cfg->two_square_rule;
+  rules.sampler = cfg->sampler;
+  rules.chasing = cfg->chasing_rule;
+  rules.acting_obs = cfg->acting_obs_only;
+  // zero this call's work counters (a kernel rather than a memset, so that the
+  // call can be captured into a graph)
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nplies, 256)), dim3(256), 0, s,
+                     reinterpret_cast<int32_t*>(d->scratch), nplies, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t*>(d->scratch + kStaticErr), 2,
+                     INT_MAX);
+  if (hipGetLastError() != hipSuccess) return STRATEGO_E_HIP;
+  for (int p = 0; p < nplies; ++p) {
+    PlyArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.states = reinterpret_cast<uint8_t*>(states_dev);
+    a.n = n;
+    a.total = n;
+    a.err = reinterpret_cast<int32_t*>(d->scratch + kStaticErr);
+    a.rules = rules;
+    a.out_base = p * n;
+    a.mask = mask;
+    a.num_legal = num_legal;
+    a.actions_out = actions;
+    a.obs = obs;
+    a.done = done;
+    a.outcome = outcome;
+    a.reason = reason;
+    a.ep_len = ep_len;
+    a.tickets = obs ? d->scratch + p : nullptr;   // as in stratego_run_plies
+    rc = launch_ply(d->lim, s, kFused, a, G, S, true, obs == nullptr);
+    if (rc != STRATEGO_OK) return rc;
+  }
   return STRATEGO_OK;
 }
 

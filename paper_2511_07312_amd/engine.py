@@ -27,6 +27,7 @@ RECORD_BYTES = 1536
 OBS_BYTES_PER_GAME = 97600
 HISTORY_BYTES_PER_GAME_STEP = 1544
 MAX_LEGAL = 256
+STATIC_MAX_PLIES = 4096
 SAMPLER_UNIFORM = 0
 SAMPLER_MAGNET = 1
 
@@ -39,6 +40,7 @@ FUNCTIONS = [
     "stratego_history_legal_mask", "stratego_history_encode_obs", "stratego_history_info",
     "stratego_history_export", "stratego_legal_list", "stratego_magnet_policy",
     "stratego_search_policy", "stratego_sample_policy", "stratego_board_strings",
+    "stratego_run_plies_static",
 ]
 REQ_STEP = 0
 REQ_ROLLOUT = 1
@@ -139,6 +141,7 @@ def load_library(path=LIB_PATH):
     L.stratego_search_policy.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, P]
     L.stratego_sample_policy.argtypes = [P, P, P]
     L.stratego_board_strings.argtypes = [P, I64, P, I32, ctypes.c_char_p]
+    L.stratego_run_plies_static.argtypes = [ctypes.POINTER(StrategoConfig), P, P, I32, P, P, P, P, P, P, P, P]
     L.stratego_strerror.argtypes = [ctypes.c_int]
     L.stratego_strerror.restype = ctypes.c_char_p
     for f in FUNCTIONS:
@@ -354,6 +357,27 @@ def stratego_run_plies(ctx, nplies, mask=None, num_legal=None, actions=None, obs
         _ptr(reason, torch.uint8, per, "reason"), _ptr(ep_len, torch.int16, per, "ep_len"),
         int(bool(use_graph)), _ptr(ply_ns, torch.int64, int(nplies), "ply_ns")),
         "stratego_run_plies")
+
+
+def stratego_run_plies_static(states, nplies, seed, k_battleless=100, max_moves=4000, auto_reset=False,
+                              games_per_wg=0, lds_layout=0, two_square=False, sampler=SAMPLER_UNIFORM,
+                              chasing=False, acting_obs=False, mask=None, num_legal=None, actions=None,
+                              obs=None, done=None, outcome=None, reason=None, ep_len=None):
+    """Fused plies over caller-owned records (uint8 [N, 1536] on the GPU), on
+    torch's current stream, without allocation or a context."""
+    n = int(states.shape[0])
+    per = int(nplies) * n
+    cfg = StrategoConfig(n, int(k_battleless), int(max_moves), int(bool(auto_reset)), int(seed), 0,
+                         int(games_per_wg), int(lds_layout), 0, int(bool(two_square)), int(sampler),
+                         int(bool(chasing)), int(bool(acting_obs)))
+    obs_bytes = OBS_BYTES_PER_GAME // 2 if acting_obs else OBS_BYTES_PER_GAME
+    _check(load_library().stratego_run_plies_static(
+        ctypes.byref(cfg), _stream(), _ptr(states, torch.uint8, n * RECORD_BYTES, "states"), int(nplies),
+        _ptr(mask, torch.int64, n * MASK_WORDS, "mask"), _ptr(num_legal, torch.int16, n, "num_legal"),
+        _ptr(actions, torch.int16, per, "actions"), _ptr(obs, torch.uint8, n * obs_bytes, "obs"),
+        _ptr(done, torch.int8, per, "done"), _ptr(outcome, torch.int8, per, "outcome"),
+        _ptr(reason, torch.uint8, per, "reason"), _ptr(ep_len, torch.int16, per, "ep_len")),
+        "stratego_run_plies_static")
 
 
 def stratego_run_plies_slots(ctx, slots, nplies, mask=None, actions=None, obs=None, done=None,
