@@ -4,7 +4,8 @@ Metric: game steps per second at 65,536 games, where one game step is a legal
 mask of the player to move + a uniform Philox sample + the step (battle,
 terminal and draw checks, auto-reset) + the uint8 observation encoding
 [2, 488, 10, 10] of both players.  The timed engine is the fused persistent
-kernel, one launch per ply, replayed from hipGraphs of 64 plies.  Inputs are
+kernel, one launch per ply, replayed from hipGraphs of up to 64 plies; exactly
+--steps plies are timed after exactly --warmup plies.  Inputs are
 synthetic: uniform random setups from the seed and uniform random legal play.
 
 Prints one JSON line.  Also reports per-ply p50/p99 latency (device
@@ -44,6 +45,14 @@ def percentile(xs, q):
     lo = int(k)
     hi = min(lo + 1, len(xs) - 1)
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def graph_split(steps):
+    """The timed plies run from `full` graphs of P plies and, for the
+    remainder, one graph of R plies: P * full + R == steps exactly."""
+    P = min(GRAPH_PLIES, steps)
+    full, R = divmod(steps, P)
+    return P, full, R
 
 
 def traffic_from_profile():
@@ -403,9 +412,11 @@ def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
     return out
 
 
-def other_seeds_bench(E, torch, G, S, n=GAMES, seeds=(2, 3), warm=1024, timed=640):
-    """The headline workload with other seeds (shorter runs, the tuned tiling):
-    the rate does not depend on the seed."""
+def steady_state_bench(E, torch, G, S, n=GAMES, seeds=(1, 2, 3), warm=1024, timed=640):
+    """The headline workload at its steady state, per seed (the tuned tiling):
+    1024 plies first, so that the games' episodes have desynchronised (the
+    first games end after about 200 plies and every game restarts on its own),
+    then 640 timed plies from graphs of 64."""
     out = {}
     stream = torch.cuda.current_stream()
     for seed in seeds:
@@ -428,15 +439,57 @@ def other_seeds_bench(E, torch, G, S, n=GAMES, seeds=(2, 3), warm=1024, timed=64
         eng.close()
         del obs, eng
         torch.cuda.empty_cache()
-        out[str(seed)] = dict(value=n / (ms / 1e3), ms_per_step=ms)
-    print(f"[bench] other seeds: {out}", file=sys.stderr, flush=True)
+        out[str(seed)] = dict(value=n / (ms / 1e3), ms_per_step=ms, warmup_plies=warm, timed_plies=timed)
+    print(f"[bench] steady state: {out}", file=sys.stderr, flush=True)
     return out
+
+
+def latency_bench(E, torch, eng, obs, samples=200):
+    """Per-ply latency of the fused and the plain engine measured the same way:
+    HIP events around each ply, one ply at a time (the fused ply as one direct
+    launch, the plain ply as its four calls)."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def sample(fn):
+        xs = []
+        for i in range(samples + 4):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            if i >= 4:
+                xs.append(e0.elapsed_time(e1))
+        return xs
+
+    fused = sample(lambda: E.stratego_run_plies(eng.ctx, 1, mask=eng.mask, num_legal=eng.num_legal,
+                                                obs=obs))
+
+    def plain_ply():
+        eng.legal_mask()
+        eng.sample()
+        eng.encode()
+        eng.step()
+    plain = sample(plain_ply)
+    assert eng.error() == (0, -1)
+    out = dict(method="HIP events around each ply, one ply at a time", samples=samples,
+               fused=dict(p50_ms=percentile(fused, 0.5), p99_ms=percentile(fused, 0.99),
+                          value=n_rate(eng.n, fused)),
+               plain=dict(p50_ms=percentile(plain, 0.5), p99_ms=percentile(plain, 0.99),
+                          value=n_rate(eng.n, plain),
+                          engine="plain per-call kernels (legal_mask, sample, encode_obs, step)"))
+    print(f"[bench] latency: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def n_rate(n, ms_list):
+    return n / (sum(ms_list) / len(ms_list) / 1e3)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6400, help="timed plies (multiple of 64)")
+    ap.add_argument("--steps", type=int, default=6400, help="timed plies")
     ap.add_argument("--warmup", type=int, default=1024, help="untimed plies before timing")
     ap.add_argument("--games", type=int, default=GAMES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -461,9 +514,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     n = args.games
-    steps = max(GRAPH_PLIES, (args.steps // GRAPH_PLIES) * GRAPH_PLIES)
+    steps = max(1, args.steps)
+    warmup = max(0, args.warmup)
+    P, full, R = graph_split(steps)
     eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=True)
-    P = GRAPH_PLIES
     acts = torch.empty((P, n), dtype=torch.int16, device="cuda")
     done = torch.empty((P, n), dtype=torch.int8, device="cuda")
     outc = torch.empty((P, n), dtype=torch.int8, device="cuda")
@@ -472,10 +526,10 @@ def main():
     ply_ns = torch.empty(P, dtype=torch.int64, device="cuda")
     obs = eng.obs
 
-    def graph_plies(timed):
-        E.stratego_run_plies(eng.ctx, P, mask=eng.mask, num_legal=eng.num_legal, actions=acts,
+    def plies(k, use_graph, timed=False):
+        E.stratego_run_plies(eng.ctx, k, mask=eng.mask, num_legal=eng.num_legal, actions=acts,
                              obs=obs, done=done, outcome=outc, reason=reas, ep_len=epl,
-                             use_graph=True, ply_ns=ply_ns if timed else None)
+                             use_graph=use_graph, ply_ns=ply_ns[:k] if timed else None)
 
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -485,12 +539,15 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    # warm-up: desynchronise the games (boards reset independently)
-    for _ in range(max(1, args.warmup // P)):
-        graph_plies(False)
+    # warm-up: exactly `warmup` plies of the timed games (direct launches of
+    # the same fused ply); long enough ones desynchronise the episodes
+    for k0 in range(0, warmup, P):
+        plies(min(P, warmup - k0), False)
     torch.cuda.synchronize()
-    print(f"[bench] warm-up {args.warmup} plies done", file=sys.stderr, flush=True)
+    print(f"[bench] warm-up {warmup} plies done", file=sys.stderr, flush=True)
 
+    # tiling: the autotuner times every tiling on the current states and
+    # restores them afterwards, so its plies do not advance the timed games
     tune = []
     if args.tiling:
         g, s_ = (int(x) for x in args.tiling.split(","))
@@ -498,11 +555,14 @@ def main():
     elif not args.no_tune:
         tune = E.stratego_autotune(eng.ctx, obs, eng.mask, plies=8)
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
+    tuning_plies = 9 * len(tune)
     G, S = E.stratego_get_tiling(eng.ctx)
-    graph_plies(True)                       # capture the graph for the chosen tiling
+    plies(P, 2, True)                       # build the graphs for the chosen tiling
+    if R:
+        plies(R, 2, True)
     torch.cuda.synchronize()
 
-    # timed region
+    # timed region: exactly `steps` plies
     lat = []
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -511,15 +571,16 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     per_launch = []
-    for _ in range(steps // P):
-        graph_plies(True)
-        per_launch.append(ply_ns.clone())
+    for k in [P] * full + ([R] if R else []):
+        plies(k, True, True)
+        per_launch.append(ply_ns[:k].clone())
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     for t in per_launch:
         lat += [x / 1e6 for x in t.cpu().tolist()]
+    assert len(lat) == steps
     assert eng.error() == (0, -1)
     ms_per_step = gpu_ms / steps
     value = n * steps / (gpu_ms / 1e3)
@@ -545,26 +606,7 @@ def main():
                          fused_ply_frac=achieved / fill_gbs)
     print(f"[bench] store ceiling: {store_ceiling}", file=sys.stderr, flush=True)
 
-    plain = None
-    if not args.no_plain:
-        pl = []
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        for i in range(24):
-            e0.record(stream)
-            eng.legal_mask()
-            eng.sample()
-            eng.encode()
-            eng.step()
-            e1.record(stream)
-            e1.synchronize()
-            if i >= 4:
-                pl.append(e0.elapsed_time(e1))
-        plain = dict(value=n / (sum(pl) / len(pl) / 1e3), unit="game steps/s",
-                     p50_ms=percentile(pl, 0.5), p99_ms=percentile(pl, 0.99), plies=len(pl),
-                     engine="plain per-call kernels (legal_mask, sample, encode_obs, step)")
-        print(f"[bench] plain engine: {plain}", file=sys.stderr, flush=True)
-        assert eng.error() == (0, -1)
+    latency = None if args.no_plain else latency_bench(E, torch, eng, obs)
     eng.close()
     del obs, eng
     torch.cuda.empty_cache()
@@ -580,17 +622,21 @@ def main():
     torch.cuda.empty_cache()
     search = None if args.no_history else search_bench(E, torch)
     torch.cuda.empty_cache()
-    seeds = None if args.no_history else other_seeds_bench(E, torch, G, S, n)
+    steady = None if args.no_history else steady_state_bench(E, torch, G, S, n)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
+    steady_reached = warmup >= 1000
+    phase = ("after the episodes have desynchronised (at least 1000 plies of warm-up)" if steady_reached else
+             f"plies {warmup}..{warmup + steps - 1} of the first episodes, before the 1000-ply steady state "
+             "(see steady_state for that)")
     out = {
         "metric": "game steps/sec (mask+step+encode) at 65536 games; p50/p99 step latency",
         "value": value,
         "unit": "game steps/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": args.warmup,
+        "warmup": warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -599,13 +645,16 @@ def main():
         "data": "synthetic: uniform random setups and uniform random legal play (Philox4x32-10)",
         "config": {
             "workload": f"{n} games, fused persistent ply kernel (mask, sample, encode both "
-                        f"players [2,488,10,10] uint8, step, auto-reset), hipGraph of {P} plies",
+                        f"players [2,488,10,10] uint8, step, auto-reset), {steps} timed plies from "
+                        f"hipGraphs of {P} plies" + (f" and one of {R}" if R else "") + f"; {phase}",
             "games": n, "plies_per_graph": P, "k_battleless": K_BATTLELESS,
             "max_moves": MAX_MOVES, "seed": SEED, "games_per_wg": G, "lds_layout": S,
+            "steady_state": steady_reached, "tuning_plies_on_restored_states": tuning_plies,
             "parallelism": "single GPU",
         },
         "p50_ms": percentile(lat, 0.5),
         "p99_ms": percentile(lat, 0.99),
+        "latency_method": "device timestamps of each ply kernel (first wave start to last wave end)",
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -616,14 +665,14 @@ def main():
             "kernel_ms_device_timestamps": kernel_ms,
         },
         "store_ceiling": store_ceiling,
-        "plain_engine": plain,
+        "latency_fused_vs_plain": latency,
+        "steady_state": steady,
         "acting_player_only": acting,
         "serving": serving,
         "rollout_buffer": rollout_buffer,
         "competitive_rules": two_square,
         "policies": policies,
         "search_shaped": search,
-        "other_seeds": seeds,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }

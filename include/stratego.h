@@ -168,10 +168,13 @@ int stratego_export_states(stratego_ctx* ctx, void* states_dev);
  * hold the last ply's values); actions/done/outcome/reason/ep_len are written
  * per ply as [nplies][N] arrays.  Any output may be NULL (obs_dev NULL skips
  * the encoding).  With use_graph = 1 the nplies launches are captured once
- * into a hipGraph (per distinct argument set) and replayed.  ply_ns_dev, if
+ * into a hipGraph (per distinct argument set) and replayed; use_graph = 2
+ * only builds and uploads that graph (nothing runs, no game advances), so
+ * that a later use_graph = 1 call with the same arguments starts at once.
+ * ply_ns_dev, if
  * not NULL, receives int64[nplies] per-ply device durations in nanoseconds
- * (first wave start to last wave end).  Errors: E_INVAL (nplies < 0; nplies
- * above 4096 with use_graph or ply_ns_dev), E_HIP. */
+ * (first wave start to last wave end).  Errors: E_INVAL (nplies < 0; use_graph
+ * outside 0..2; nplies above 4096 with use_graph or ply_ns_dev), E_HIP. */
 int stratego_run_plies(stratego_ctx* ctx, int32_t nplies, uint64_t* mask_dev,
                        int16_t* num_legal_dev, int16_t* actions_dev, uint8_t* obs_dev,
                        int8_t* done_dev, int8_t* outcome_dev, uint8_t* reason_dev,

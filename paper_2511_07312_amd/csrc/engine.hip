@@ -1059,7 +1059,7 @@ int stratego_export_states(stratego_ctx* c, void* states) {
 int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t* num_legal,
                        int16_t* actions, uint8_t* obs, int8_t* done, int8_t* outcome, uint8_t* reason,
                        int16_t* ep_len, int32_t use_graph, int64_t* ply_ns) {
-  if (!c || nplies < 0) return STRATEGO_E_INVAL;
+  if (!c || nplies < 0 || use_graph < 0 || use_graph > 2) return STRATEGO_E_INVAL;
   if (ply_ns && nplies > kMaxTimedPlies) return STRATEGO_E_INVAL;
   if (nplies == 0) return STRATEGO_OK;
   const bool timed = ply_ns != nullptr;
@@ -1111,6 +1111,8 @@ int stratego_run_plies(stratego_ctx* c, int32_t nplies, uint64_t* mask, int16_t*
       e.exec = exec;
       c->graphs.push_back(e);
     }
+    if (use_graph == 2)   // prepare only: the graph is built and uploaded, nothing runs
+      return hipGraphUpload(exec, c->stream) == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
     if (hipGraphLaunch(exec, c->stream) != hipSuccess) return STRATEGO_E_HIP;
   }
   if (timed) {

@@ -347,6 +347,8 @@ _ctx_obs = {}
 
 def stratego_run_plies(ctx, nplies, mask=None, num_legal=None, actions=None, obs=None, done=None,
                        outcome=None, reason=None, ep_len=None, use_graph=False, ply_ns=None):
+    """use_graph: False/0 direct launches, True/1 replay a captured graph, 2
+    build and upload the graph only (nothing runs)."""
     n = _num_games(ctx)
     per = None if n is None else int(nplies) * n
     _check(load_library().stratego_run_plies(
@@ -355,7 +357,7 @@ def stratego_run_plies(ctx, nplies, mask=None, num_legal=None, actions=None, obs
         _ptr(obs, torch.uint8, n and n * obs_bytes_per_game(ctx), "obs"),
         _ptr(done, torch.int8, per, "done"), _ptr(outcome, torch.int8, per, "outcome"),
         _ptr(reason, torch.uint8, per, "reason"), _ptr(ep_len, torch.int16, per, "ep_len"),
-        int(bool(use_graph)), _ptr(ply_ns, torch.int64, int(nplies), "ply_ns")),
+        int(use_graph), _ptr(ply_ns, torch.int64, int(nplies), "ply_ns")),
         "stratego_run_plies")
 
 

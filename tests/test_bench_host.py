@@ -49,3 +49,12 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_graph_split_times_exactly_the_requested_plies():
+    for steps in (1, 5, 20, 63, 64, 65, 100, 6400, 6401):
+        P, full, R = bench.graph_split(steps)
+        assert P * full + R == steps
+        assert 1 <= P <= bench.GRAPH_PLIES and 0 <= R < P
+    assert bench.graph_split(20) == (20, 1, 0)
+    assert bench.graph_split(6400) == (64, 100, 0)
