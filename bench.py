@@ -414,9 +414,9 @@ def search_bench(E, torch, n_src=1024, per=256, plies=50, reps=4):
 
 def steady_state_bench(E, torch, G, S, n=GAMES, seeds=(1, 2, 3), warm=1024, timed=640):
     """The headline workload at its steady state, per seed (the tuned tiling):
-    1024 plies first, so that the games' episodes have desynchronised (the
-    first games end after about 200 plies and every game restarts on its own),
-    then 640 timed plies from graphs of 64."""
+    1024 plies first, so that the games' episodes have desynchronised (random
+    games last about 490 plies on average and at most 1000, and every game
+    restarts on its own), then 640 timed plies from graphs of 64."""
     out = {}
     stream = torch.cuda.current_stream()
     for seed in seeds:

@@ -14,6 +14,7 @@ from .oracle import (  # noqa: F401
     setup_types,
     hidden_prob,
     fnv1a64,
+    digest_blocks,
     num_threads,
     REC_BYTES,
     MASK_WORDS,

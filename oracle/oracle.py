@@ -80,6 +80,7 @@ def lib():
                                       ctypes.c_int, P]
         L.orc_hidden_prob.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
+        L.orc_digest_blocks.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P]
         L.orc_fnv1a64.argtypes = [P, ctypes.c_size_t]
         L.orc_fnv1a64.restype = ctypes.c_uint64
         L.orc_board_string.argtypes = [P, ctypes.c_char_p]
@@ -118,6 +119,16 @@ def num_threads():
 def fnv1a64(buf):
     b = np.ascontiguousarray(buf).view(np.uint8)
     return int(lib().orc_fnv1a64(_p(b), b.nbytes))
+
+
+def digest_blocks(buf, block):
+    """Per-block digests (uint64) of a byte buffer cut into blocks of `block`
+    bytes: sum of byte i times the SplitMix64 weight of i, modulo 2^64."""
+    b = np.ascontiguousarray(buf).reshape(-1).view(np.uint8)
+    assert b.size % block == 0
+    out = np.zeros(b.size // block, dtype=np.uint64)
+    lib().orc_digest_blocks(_p(b), b.size // block, int(block), _p(out))
+    return out
 
 
 def hidden_prob(engine, game, w, moved, t):
@@ -214,13 +225,19 @@ class OracleEngine:
         lib().orc_batch_resample(_p(self.states), self.n, per, seed, game_id_base, _p(out.states))
         return out
 
-    def ply(self, obs=True, mask=True):
+    def ply(self, obs=True, mask=True, obs_out=None):
+        """One fused ply; obs_out, if given, is a reused uint8 buffer for the
+        observations (then returned as r["obs"])."""
         n = self.n
+        if obs and obs_out is not None:
+            assert obs_out.dtype == np.uint8 and obs_out.flags.c_contiguous
+            assert obs_out.size == n * self.observers * NCHAN * 100
         r = dict(
             mask=np.zeros((n, MASK_WORDS), dtype=np.uint64) if mask else None,
             num_legal=np.zeros(n, dtype=np.int16),
             actions=np.zeros(n, dtype=np.int16),
-            obs=np.zeros((n, self.observers, NCHAN, 10, 10), dtype=np.uint8) if obs else None,
+            obs=(obs_out if obs_out is not None else np.zeros((n, self.observers, NCHAN, 10, 10), dtype=np.uint8))
+            if obs else None,
             done=np.zeros(n, dtype=np.int8), outcome=np.zeros(n, dtype=np.int8),
             reason=np.zeros(n, dtype=np.uint8), ep_len=np.zeros(n, dtype=np.int16))
         lib().orc_batch_ply(_p(self.states), n, self._cfgp(), _p(r["mask"]), _p(r["num_legal"]),

@@ -1369,6 +1369,33 @@ uint64_t orc_fnv1a64(const uint8_t* buf, size_t len) {
     return h;
 }
 
+/* Test support, not part of the method: a 64-bit digest of each of `count`
+ * consecutive blocks of `block` bytes, the sum over the block of byte i times
+ * w(i) modulo 2^64, where w(i) is the SplitMix64 output for the counter value
+ * i + 1 (Steele, Lea and Flood, OOPSLA 2014).  Pseudo-random weights make
+ * distinct blocks collide only by chance.  The tests form the same sum on the
+ * device, so that observations can be compared without copying them out. */
+static uint64_t digest_weight(uint64_t i) {
+    uint64_t z = (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void orc_digest_blocks(const uint8_t* data, int64_t count, int64_t block, uint64_t* out) {
+    uint64_t* w = (uint64_t*)malloc((size_t)block * sizeof(uint64_t));
+    if (!w) return;
+    for (int64_t i = 0; i < block; i++) w[i] = digest_weight((uint64_t)i);
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < count; b++) {
+        const uint8_t* p = data + b * block;
+        uint64_t sum = 0;
+        for (int64_t i = 0; i < block; i++) sum += (uint64_t)p[i] * w[i];
+        out[b] = sum;
+    }
+    free(w);
+}
+
 /* Human-readable board (App. B "BoardStrs" debugging aid): rows 9..0 top to
  * bottom, three characters per square: owner ('r'/'b') and type symbol
  * (S 2-9 M F B), "~~" lake, ".." empty. */

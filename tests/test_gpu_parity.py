@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from digest import DeviceDigest
 from positions import header, make_record, sq
 
 torch = pytest.importorskip("torch")
@@ -145,13 +146,15 @@ def test_game_id_offset_shards_match_single_context():
 
 
 # ---------------------------------------------------------------- play to the end
-def test_4096_games_to_terminal_histograms():
+def test_4096_games_to_terminal_every_ply():
     """4096 games of random play without auto-reset until every game ends (or the
-    1000-ply cap), one fused ply per launch: every ply's actions and done flags,
-    the observations of 64 games (a different 64 each ply) and of all games at
-    a few plies equal the oracle's, as do the final states and the
-    outcome/reason and game-length histograms."""
-    n, seed, sub = 4096, 2, 64
+    1000-ply cap), one fused ply per launch.  Every ply, for every game: the
+    mask, num_legal, action and step outputs, the record after the ply, and a
+    digest of each observer's full observation (sum of the 48,800 bytes with
+    SplitMix64 weights modulo 2^64, formed on the device and by the oracle
+    library) equal the oracle's; the full observation bytes too at a few plies;
+    then the outcome/reason and game-length histograms."""
+    n, seed = 4096, 2
     eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=False)
     ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=False)
     acts = torch.empty((1, n), dtype=torch.int16, device="cuda")
@@ -159,25 +162,28 @@ def test_4096_games_to_terminal_histograms():
     outc = torch.empty((1, n), dtype=torch.int8, device="cuda")
     reas = torch.empty((1, n), dtype=torch.uint8, device="cuda")
     epl = torch.empty((1, n), dtype=torch.int16, device="cuda")
-    full_obs_at = {0, 1, 2, 49, 99, 149, 399, 699}
+    ddig = DeviceDigest(torch, E.OBS_BYTES_PER_GAME // 2)
+    obs_buf = np.empty((n, 2, 488, 10, 10), dtype=np.uint8)
+    full_obs_at = {0, 1, 99, 399}
     ply = 0
     while True:
-        E.stratego_run_plies(eng.ctx, 1, actions=acts, obs=eng.obs, done=done, outcome=outc,
-                             reason=reas, ep_len=epl)
-        r = ref.ply(obs=True, mask=False)
+        E.stratego_run_plies(eng.ctx, 1, mask=eng.mask, num_legal=eng.num_legal, actions=acts, obs=eng.obs,
+                             done=done, outcome=outc, reason=reas, ep_len=epl)
+        r = ref.ply(obs=True, mask=True, obs_out=obs_buf)
+        assert_same(f"mask@{ply}", cpu(eng.mask), r["mask"])
+        assert_same(f"num_legal@{ply}", cpu(eng.num_legal), r["num_legal"])
         assert_same(f"actions@{ply}", cpu(acts[0]), r["actions"])
-        assert_same(f"done@{ply}", cpu(done[0]), r["done"])
+        for name, t in (("done", done), ("outcome", outc), ("reason", reas), ("ep_len", epl)):
+            assert_same(f"{name}@{ply}", cpu(t[0]), r[name])
+        assert_same(f"obs digests@{ply}", ddig(eng.obs).reshape(n, 2),
+                    O.digest_blocks(obs_buf, E.OBS_BYTES_PER_GAME // 2).reshape(n, 2))
         if ply in full_obs_at:
-            assert_same(f"obs@{ply}", cpu(eng.obs), r["obs"])
-        else:
-            games = (np.arange(sub) * (n // sub) + ply) % n
-            idx = torch.from_numpy(games).cuda()
-            assert_same(f"obs@{ply} (64 games)", cpu(eng.obs[idx]), r["obs"][games])
+            assert_same(f"obs@{ply}", cpu(eng.obs), obs_buf)
+        assert_same(f"records@{ply}", cpu(eng.export()), ref.export())
         ply += 1
         if cpu(done[0]).all():
             break
         assert ply <= 1000
-    assert_same("final states", cpu(eng.export()), ref.export())
     d_out, d_rsn, d_len = cpu(outc[0]), cpu(reas[0]), cpu(epl[0])
     recs = ref.export()
     hs = [header(recs[g]) for g in range(n)]
@@ -189,7 +195,20 @@ def test_4096_games_to_terminal_histograms():
     assert_same("outcome x reason histogram", got_pairs, want_pairs)
     assert_same("length histogram", np.bincount(d_len.astype(np.int64), minlength=1001),
                 np.bincount(np.array([h["ply"] for h in hs]), minlength=1001))
+    assert eng.error() == (0, -1)
     eng.close()
+
+
+def test_device_digest_matches_the_oracle_digest():
+    """The device-side digest forms the oracle library's sum: both on the same
+    observation bytes, at two block sizes."""
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 256, size=(300, E.OBS_BYTES_PER_GAME // 2), dtype=np.uint8)
+    x[rng.random(x.shape) < 0.9] = 0
+    dev = torch.from_numpy(x).cuda()
+    for block in (E.OBS_BYTES_PER_GAME // 2, E.OBS_BYTES_PER_GAME):
+        assert_same(f"digest of {block}-byte blocks", DeviceDigest(torch, block, rows_per_chunk=37)(dev),
+                    O.digest_blocks(x, block))
 
 
 @pytest.mark.parametrize("n", [1, 7, 65, 1000, 5121, 20483])
@@ -466,30 +485,79 @@ def test_serving_results_same_alone_and_in_the_mix():
 
 
 # ---------------------------------------------------------------- full size
-def test_65536_games_graph_plies_sampled_against_oracle():
-    """The benchmark's configuration (65,536 games, auto-reset, 64-ply hipGraph
-    launches, autotuned tiling): 600 sampled games, checked one by one against
-    the oracle playing only those game ids, on the final records after 128 plies
-    and on the last ply's mask, actions and both observations."""
-    n, seed, P = 65536, 1, 64
+def test_65536_games_whole_population_graph_plies():
+    """The benchmark's configuration (65,536 games, auto-reset, autotuned
+    tiling, 64-ply hipGraph launches) against the oracle playing all 65,536
+    games: over 192 plies every game's action, done flag and outcome every
+    ply, every record after each graph launch, and at the last ply every
+    game's mask and both observations, byte for byte."""
+    n, seed, P, launches = 65536, 1, 64, 3
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
+    E.stratego_autotune(eng.ctx, eng.obs, eng.mask, plies=2)
+    G, S = E.stratego_get_tiling(eng.ctx)
+    print(f"tiling G={G} layout={S}", flush=True)
+    acts = torch.empty((P, n), dtype=torch.int16, device="cuda")
+    done = torch.empty((P, n), dtype=torch.int8, device="cuda")
+    outc = torch.empty((P, n), dtype=torch.int8, device="cuda")
+    ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
+    chunk = 4096
+    for launch in range(launches):
+        E.stratego_run_plies(eng.ctx, P, mask=eng.mask, actions=acts, obs=eng.obs, done=done, outcome=outc,
+                             use_graph=True)
+        a_h, d_h, o_h = cpu(acts), cpu(done), cpu(outc)
+        for p in range(P):
+            ply = launch * P + p
+            last = launch == launches - 1 and p == P - 1
+            if last:   # the last ply's observations and mask are of its pre-move states
+                for g0 in range(0, n, chunk):
+                    idx = np.arange(g0, g0 + chunk, dtype=np.int32)
+                    assert_same(f"obs@{ply} games {g0}..", cpu(eng.obs[g0:g0 + chunk]), ref.encode(idx))
+            r = ref.ply(obs=False, mask=last)
+            assert_same(f"actions@{ply}", a_h[p], r["actions"])
+            assert_same(f"done@{ply}", d_h[p], r["done"])
+            assert_same(f"outcome@{ply}", o_h[p], r["outcome"])
+            if last:
+                assert_same(f"mask@{ply}", cpu(eng.mask), r["mask"])
+        assert_same(f"records after ply {launch * P + P - 1}", cpu(eng.export()), ref.export())
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
+def test_65536_games_after_1024_plies_sampled():
+    """The desynchronised regime the benchmark times: 65,536 games, auto-reset,
+    autotuned tiling, 1,088 plies from 64-ply graphs; 2,048 games spread over
+    the slots, each checked against the oracle playing only those game ids:
+    the last 64 plies' actions and done flags, the final records, and the last
+    ply's mask and both observations."""
+    n, seed, P = 65536, 3, 64
     eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True)
     E.stratego_autotune(eng.ctx, eng.obs, eng.mask, plies=2)
     acts = torch.empty((P, n), dtype=torch.int16, device="cuda")
-    for _ in range(2):
-        E.stratego_run_plies(eng.ctx, P, mask=eng.mask, num_legal=eng.num_legal, actions=acts,
-                             obs=eng.obs, use_graph=True)
-    rng = np.random.default_rng(0)
-    ids = np.sort(rng.choice(n, size=600, replace=False)).astype(np.int64)
+    done = torch.empty((P, n), dtype=torch.int8, device="cuda")
+    launches = 17
+    for _ in range(launches):
+        E.stratego_run_plies(eng.ctx, P, mask=eng.mask, actions=acts, obs=eng.obs, done=done, use_graph=True)
+    rng = np.random.default_rng(7)
+    ids = np.sort(rng.choice(n, size=2048, replace=False)).astype(np.int64)
     idx = torch.from_numpy(ids).cuda()
     ref = O.OracleEngine(len(ids), seed, k_battleless=100, max_moves=1000, auto_reset=True,
                          game_ids=ids.astype(np.uint32))
-    for p in range(2 * P):
-        r = ref.ply(obs=(p == 2 * P - 1))
-        if p >= P:
-            assert_same(f"actions@{p}", cpu(acts[p - P].index_select(0, idx)), r["actions"])
+    total = launches * P
+    for p in range(total):
+        last = p == total - 1
+        r = ref.ply(obs=last, mask=last)
+        if p >= total - P:
+            assert_same(f"actions@{p}", cpu(acts[p - total + P].index_select(0, idx)), r["actions"])
+            assert_same(f"done@{p}", cpu(done[p - total + P].index_select(0, idx)), r["done"])
     assert_same("last mask", cpu(eng.mask.index_select(0, idx)), r["mask"])
     assert_same("last obs", cpu(eng.obs.index_select(0, idx)), r["obs"])
-    assert_same("records", cpu(eng.export().index_select(0, idx)), ref.export())
+    recs = cpu(eng.export().index_select(0, idx))
+    assert_same("records", recs, ref.export())
+    hs = [header(recs[g]) for g in range(len(ids))]
+    # desynchronised: every game has restarted (no game lasts more than 1000
+    # plies) and the games stand at many different plies of their episodes
+    assert min(h["episode"] for h in hs) >= 1
+    assert len({h["ply"] for h in hs}) > 300
     assert eng.error() == (0, -1)
     eng.close()
 
