@@ -123,6 +123,16 @@ constexpr int kMaxLegal = 256;   // legal-list capacity (at most 244 legal moves
 // ---------------------------------------------------------------- wave helpers
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// The lane id, made opaque where it is used: the empty asm statement hides the
+// value from the optimiser, so that the many values derived from it (square
+// numbers, neighbours, lane masks) are computed per game instead of being
+// hoisted out of the per-game loop and kept live, and spilled, across it.
+__device__ __forceinline__ int lane_here() {
+  int l = lane_id();
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 // Order LDS traffic between the lanes of one wavefront.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -145,6 +155,20 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Inclusive prefix sum over the 64 lanes by DPP lane moves, which take no LDS
+// round trip: Hillis-Steele steps of 1, 2, 4, 8 lanes inside each row of 16,
+// then the totals of row 0 into row 1 and of row 2 into row 3 (lane 15 of a row
+// to the next row), then lane 31's running total into rows 2 and 3.
+__device__ __forceinline__ int dpp_incl_scan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
   return v;
 }
 
@@ -1024,6 +1048,545 @@ __device__ __forceinline__ StepOut step_game(uint8_t* R, uint8_t* scratch, uint8
       reset_game(R, scratch, work, rules, hdr_u32(R, kOffGameId), hdr_u32(R, kOffEpisode) + 1,
                  hdr_u32(R, kOffRedraws));
   }
+  return o;
+}
+
+// ---------------------------------------------------------------- register boards
+// Fast path of the fused ply while neither competitive-play rule is on.  The
+// game's squares sit in registers (lane l holds squares l and 64 + l: the
+// piece id and that piece's word 0) and each player's pieces form wave-uniform
+// 100-square sets built by ballots.  Legal destinations become bit tests on
+// those sets, the no-move test of the terminal check set arithmetic, and a
+// look-up at a square the whole wave agrees on a lane read (v_readlane)
+// instead of a chain of dependent LDS loads.  The record in LDS stays the
+// state and is written exactly as the general path writes it.
+struct Set100 {
+  uint64_t lo, hi;   // squares 0-63 in lo, squares 64-99 in bits 0-35 of hi
+};
+constexpr uint64_t kHi36 = (1ull << 36) - 1;
+
+__host__ __device__ constexpr Set100 column_set(int c) {
+  Set100 s{0, 0};
+  for (int r = 0; r < 10; ++r) {
+    const int x = 10 * r + c;
+    if (x < 64) s.lo |= 1ull << x;
+    else s.hi |= 1ull << (x - 64);
+  }
+  return s;
+}
+constexpr Set100 kCol0 = column_set(0), kCol9 = column_set(9);
+constexpr Set100 kLakeSet = {(1ull << 42) | (1ull << 43) | (1ull << 46) | (1ull << 47) | (1ull << 52) |
+                                 (1ull << 53) | (1ull << 56) | (1ull << 57),
+                             0};
+constexpr Set100 kAllSquares = {~0ull, kHi36};
+
+__device__ __forceinline__ Set100 s_or(Set100 a, Set100 b) { return Set100{a.lo | b.lo, a.hi | b.hi}; }
+__device__ __forceinline__ Set100 s_and(Set100 a, Set100 b) { return Set100{a.lo & b.lo, a.hi & b.hi}; }
+__device__ __forceinline__ Set100 s_andnot(Set100 a, Set100 b) { return Set100{a.lo & ~b.lo, a.hi & ~b.hi}; }
+__device__ __forceinline__ bool s_any(Set100 a) { return (a.lo | a.hi) != 0; }
+__device__ __forceinline__ bool s_has(Set100 s, int y) {
+  return ((y < 64 ? s.lo >> y : s.hi >> (y - 64)) & 1ull) != 0;
+}
+// each square y moved to y + 10, y - 10, y + 1 (same row) and y - 1 (same row)
+__device__ __forceinline__ Set100 s_up(Set100 s) { return Set100{s.lo << 10, ((s.hi << 10) | (s.lo >> 54)) & kHi36}; }
+__device__ __forceinline__ Set100 s_down(Set100 s) { return Set100{(s.lo >> 10) | (s.hi << 54), s.hi >> 10}; }
+__device__ __forceinline__ Set100 s_right(Set100 s) {
+  s = s_andnot(s, kCol9);
+  return Set100{s.lo << 1, ((s.hi << 1) | (s.lo >> 63)) & kHi36};
+}
+__device__ __forceinline__ Set100 s_left(Set100 s) {
+  s = s_andnot(s, kCol0);
+  return Set100{(s.lo >> 1) | (s.hi << 63), s.hi >> 1};
+}
+// squares orthogonally next to a square of s
+__device__ __forceinline__ Set100 s_nbrs(Set100 s) { return s_or(s_or(s_up(s), s_down(s)), s_or(s_left(s), s_right(s))); }
+
+// The squares in registers: lane l holds squares l and 64 + l.
+struct SquareRegs {
+  int id[2];        // board entry of the square (kLake beyond square 99)
+  uint32_t w0[2];   // word 0 of the piece there, 0 without one
+  int tid[2];       // board entry of the square whose column-major index
+                    // 10 * column + row is lane (resp. 64 + lane)
+};
+
+__device__ __forceinline__ Set100 ballot100(bool b0, bool b1) { return Set100{ballot(b0), ballot(b1) & kHi36}; }
+
+__device__ __forceinline__ void load_regs(const uint8_t* R, SquareRegs& q) {
+  const int lane = lane_here();
+  q.id[0] = board_at(R, lane);
+  q.id[1] = lane < kSquares - 64 ? board_at(R, 64 + lane) : kLake;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = lane + 64 * h;   // column-major index: column t / 10, row t % 10
+    q.tid[h] = t < kSquares ? board_at(R, 10 * (t % 10) + t / 10) : kLake;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) q.w0[h] = q.id[h] >= 0 ? piece_words(R, q.id[h])[0] : 0u;
+}
+
+__device__ __forceinline__ bool owned_by(int id, int p) { return id >= 0 && owner(id) == p; }
+
+// Squares holding player p's pieces, and the empty squares.
+__device__ __forceinline__ Set100 occupied(const SquareRegs& q, int p) {
+  return ballot100(owned_by(q.id[0], p), owned_by(q.id[1], p));
+}
+__device__ __forceinline__ Set100 empty_set(const SquareRegs& q) {
+  return ballot100(q.id[0] == kEmpty, q.id[1] == kEmpty);
+}
+
+// A register value at a square the whole wave agrees on.
+__device__ __forceinline__ int reg_at(const int v[2], int y) {
+  return __builtin_amdgcn_readlane(y < 64 ? v[0] : v[1], y & 63);
+}
+__device__ __forceinline__ uint32_t reg_at(const uint32_t v[2], int y) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)(y < 64 ? v[0] : v[1]), y & 63);
+}
+
+// 64 bits of a 100-square set starting at square s (0 <= s < 128; squares
+// past 99 read as absent).
+__device__ __forceinline__ uint64_t s_window(Set100 v, int s) {
+  if (s >= 64) return v.hi >> (s - 64);
+  return s == 0 ? v.lo : (v.lo >> s) | (v.hi << (64 - s));
+}
+
+// Length of the run of squares of `open` going up from index i + 1 (at most
+// room), and whether the square after it is in `stop` (a capture).
+__device__ __forceinline__ int run_up(Set100 open, Set100 stop, int i, int room, int& cap) {
+  int run = __builtin_ctzll(~s_window(open, i + 1));
+  run = run < room ? run : room;
+  cap = run < room && s_has(stop, i + 1 + run) ? 1 : 0;
+  return run;
+}
+// The same going down from index i - 1 (room = squares below i in its line).
+__device__ __forceinline__ int run_down(Set100 open, Set100 stop, int i, int room, int& cap) {
+  if (room == 0) { cap = 0; return 0; }
+  const uint64_t m = (1ull << room) - 1;
+  const uint64_t gaps = ~s_window(open, i - room) & m;   // bit j: index i - room + j not open
+  const int run = gaps == 0 ? room : room - 1 - (63 - __builtin_clzll(gaps));
+  cap = run < room && s_has(stop, i - 1 - run) ? 1 : 0;
+  return run;
+}
+
+// Destination sets of player p's pieces on the lane's two squares (App. A
+// movement rules, as destinations()): d[0..1] for square lane, d[2..3] for
+// square 64 + lane; all empty for a finished game.
+__device__ __forceinline__ void fast_dests(const SquareRegs& q, int p, bool done, uint64_t d[4]) {
+  const int lane = lane_here();
+  const Set100 empty = empty_set(q);
+  const Set100 target = s_or(empty, occupied(q, 1 - p));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int x = lane + 64 * h;
+    uint64_t lo = 0, hi = 0;
+    const int t = p_type(q.w0[h]);
+    if (!done && owned_by(q.id[h], p) && movable_type(t)) {
+      const int reach = t == kScout ? 9 : 1;
+      const int r = x / 10, c = x - 10 * r;
+#pragma unroll
+      for (int dir = 0; dir < 4; ++dir) {
+        const int delta = dir == 0 ? 10 : dir == 1 ? -10 : dir == 2 ? -1 : 1;
+        const int room = dir == 0 ? 9 - r : dir == 1 ? r : dir == 2 ? c : 9 - c;
+        const int steps = room < reach ? room : reach;
+        int y = x;
+        for (int k = 0; k < steps; ++k) {
+          y += delta;
+          if (!s_has(target, y)) break;
+          if (y < 64) lo |= 1ull << y;
+          else hi |= 1ull << (y - 64);
+          if (!s_has(empty, y)) break;
+        }
+      }
+    }
+    d[2 * h] = lo;
+    d[2 * h + 1] = hi;
+  }
+}
+
+// Legal moves of player p's pieces on the lane's two squares as counts per
+// direction, 4 bits each, in ascending order of destination: down (x - 10k,
+// bits 0-3), left (x - k, 4-7), right (x + k, 8-11), up (x + 10k, 12-15); 0
+// for other squares and in a finished game.  A piece other than a Scout
+// steps to a neighbouring empty or enemy square (App. A): its four tests are
+// bits of shifted copies of the target set.  A Scout runs over empty squares
+// and may end on an enemy square: its run lengths come from bit scans of the
+// empty squares, row-major along its row and column-major (the transposed
+// sets) along its column.  Sampling needs only these counts, not the sets.
+__device__ __forceinline__ int count_of(uint32_t pk) {
+  return (int)((pk & 15u) + ((pk >> 4) & 15u) + ((pk >> 8) & 15u) + (pk >> 12));
+}
+
+__device__ __forceinline__ void dir_counts(const SquareRegs& q, int p, bool done, uint32_t pk[2]) {
+  const int lane = lane_here();
+  const Set100 empty = empty_set(q);
+  const Set100 target = s_or(empty, occupied(q, 1 - p));
+  // bit x of each: the neighbour of x in that direction is a target square
+  const Set100 dn = s_up(target), lf = s_right(target), rt = s_left(target), up = s_down(target);
+  bool scout = false;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = p_type(q.w0[h]);
+    const bool mine = !done && owned_by(q.id[h], p) && movable_type(t);
+    auto bit = [&](Set100 v) { return (uint32_t)(((h == 0 ? v.lo : v.hi) >> lane) & 1ull); };
+    pk[h] = mine ? bit(dn) | bit(lf) << 4 | bit(rt) << 8 | bit(up) << 12 : 0u;
+    scout |= mine && t == kScout;
+  }
+  if (ballot(scout) == 0) return;
+  const Set100 empty_t = ballot100(q.tid[0] == kEmpty, q.tid[1] == kEmpty);
+  const Set100 target_t = s_or(empty_t, ballot100(owned_by(q.tid[0], 1 - p), owned_by(q.tid[1], 1 - p)));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (done || !owned_by(q.id[h], p) || p_type(q.w0[h]) != kScout) continue;
+    const int x = lane + 64 * h, r = x / 10, c = x - 10 * r, xt = 10 * c + r;
+    int cap;
+    uint32_t v = 0;
+    v |= (uint32_t)(run_down(empty_t, target_t, xt, r, cap) + cap);
+    v |= (uint32_t)(run_down(empty, target, x, c, cap) + cap) << 4;
+    v |= (uint32_t)(run_up(empty, target, x, 9 - c, cap) + cap) << 8;
+    v |= (uint32_t)(run_up(empty_t, target_t, xt, 9 - r, cap) + cap) << 12;
+    pk[h] = v;
+  }
+}
+
+// The k-th destination, in ascending order, of the piece on square x whose
+// counts are pk.
+__device__ __forceinline__ int kth_dest(int x, uint32_t pk, int k) {
+  const int nd = pk & 15u, nl = (pk >> 4) & 15u, nr = (pk >> 8) & 15u;
+  if (k < nd) return x - 10 * (nd - k);
+  k -= nd;
+  if (k < nl) return x - (nl - k);
+  k -= nl;
+  if (k < nr) return x + 1 + k;
+  return x + 10 * (1 + k - nr);
+}
+
+__device__ __forceinline__ int total_count(const uint32_t pk[2]) {
+  return __builtin_amdgcn_readlane(dpp_incl_scan(count_of(pk[0]) + count_of(pk[1])), 63);
+}
+
+// Uniform legal action (as sample_from_words: the r-th legal action in
+// ascending action order) from the counts.
+__device__ __forceinline__ int sample_counts(const uint32_t pk[2], int n, uint64_t seed, uint32_t game_id,
+                                             uint32_t ply, uint32_t episode) {
+  if (n <= 0) return -1;
+  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  int r = (int)mulshift(u.x, (uint32_t)n);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = count_of(pk[h]);
+    const int incl = dpp_incl_scan(c);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    if (r < total) {
+      const int L = __ffsll((unsigned long long)ballot(incl > r)) - 1;
+      const int k = r - (__builtin_amdgcn_readlane(incl, L) - __builtin_amdgcn_readlane(c, L));
+      const int x = 64 * h + L;
+      return 100 * x + kth_dest(x, (uint32_t)__builtin_amdgcn_readlane((int)pk[h], L), k);
+    }
+    r -= total;
+  }
+  return -1;
+}
+
+// Magnet policy sample (as sample_magnet) from the counts.
+__device__ __forceinline__ int magnet_counts(const uint32_t pk[2], uint64_t seed, uint32_t game_id, uint32_t ply,
+                                             uint32_t episode) {
+  const uint64_t has0 = ballot(pk[0] != 0), has1 = ballot(pk[1] != 0);
+  const int c0 = __popcll(has0), P = c0 + __popcll(has1);
+  if (P == 0) return -1;
+  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  const int r1 = (int)mulshift(u.y, (uint32_t)P);
+  const int x = r1 < c0 ? select_bit(has0, r1) : 64 + select_bit(has1, r1 - c0);
+  const uint32_t pkx = (uint32_t)__builtin_amdgcn_readlane((int)(x < 64 ? pk[0] : pk[1]), x & 63);
+  const int r2 = (int)mulshift(u.z, (uint32_t)count_of(pkx));
+  return 100 * x + kth_dest(x, pkx, r2);
+}
+
+__device__ __forceinline__ int count_dests(const uint64_t d[4]) {
+  const int c = __popcll(d[0]) + __popcll(d[1]) + __popcll(d[2]) + __popcll(d[3]);
+  return __builtin_amdgcn_readlane(dpp_incl_scan(c), 63);
+}
+
+// Uniform legal action (as sample_from_words: the r-th legal action in
+// ascending action order, r = bounded(x, n) of the move counter) from the
+// destination sets: squares in ascending order, then destinations.
+__device__ __forceinline__ int sample_dests(const uint64_t d[4], int n, uint64_t seed, uint32_t game_id,
+                                            uint32_t ply, uint32_t episode) {
+  if (n <= 0) return -1;
+  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  int r = (int)mulshift(u.x, (uint32_t)n);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = __popcll(d[2 * h]) + __popcll(d[2 * h + 1]);
+    const int incl = dpp_incl_scan(c);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    if (r < total) {
+      const int L = __ffsll((unsigned long long)ballot(incl > r)) - 1;
+      const int k = r - __shfl(incl - c, L, 64);
+      const uint64_t lo = __shfl(d[2 * h], L, 64), hi = __shfl(d[2 * h + 1], L, 64);
+      const int nlo = __popcll(lo);
+      const int to = k < nlo ? select_bit(lo, k) : 64 + select_bit(hi, k - nlo);
+      return 100 * (64 * h + L) + to;
+    }
+    r -= total;
+  }
+  return -1;
+}
+
+// Mask words from the destination sets, parked in ts (LDS) as
+// legal_mask_words parks them.
+__device__ __forceinline__ void words_from_dests(const uint64_t d[4], uint64_t* ts, uint64_t w[3]) {
+  const int lane = lane_here();
+  ts[2 * lane] = d[0];
+  ts[2 * lane + 1] = d[1];
+  if (lane + 64 < kSquares) {
+    ts[2 * (lane + 64)] = d[2];
+    ts[2 * (lane + 64) + 1] = d[3];
+  }
+  if (lane == 0) { ts[200] = 0; ts[201] = 0; }
+  wave_sync();
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const int word = lane + 64 * g;
+    uint64_t v = 0;
+    if (word < kMaskWords) {
+      const int a0 = 64 * word;
+      const int f0 = a0 / 100;
+      const int off = a0 - 100 * f0;
+      const uint64_t lo = ts[2 * f0], hi = ts[2 * f0 + 1];
+      v = off == 0 ? lo : off < 64 ? (lo >> off) | (hi << (64 - off)) : hi >> (off - 64);
+      const int rem = 100 - off;
+      if (rem < 64) v |= ts[2 * (f0 + 1)] << rem;
+    }
+    w[g] = v;
+  }
+}
+
+// Player p has a legal move (no competitive-play rule): a movable piece next
+// to an empty or enemy square.
+__device__ __forceinline__ bool fast_has_move(const SquareRegs& q, int p) {
+  const Set100 target = s_or(empty_set(q), occupied(q, 1 - p));
+  const Set100 mov = ballot100(owned_by(q.id[0], p) && movable_type(p_type(q.w0[0])),
+                               owned_by(q.id[1], p) && movable_type(p_type(q.w0[1])));
+  return s_any(s_and(mov, s_nbrs(target)));
+}
+
+// apply_action for the fast path, from the registers of the pre-move state:
+// the same history features, battle, death records, ring and counters, and
+// the terminal check, written to the record.  The registers are left holding
+// the post-move squares.  Returns done/outcome/reason.
+struct FastOut {
+  int done, outcome, reason;
+};
+
+__device__ __forceinline__ FastOut fast_apply(uint8_t* R, Rules rules, int action, SquareRegs& q) {
+  const int lane = lane_here();
+  action = __builtin_amdgcn_readfirstlane(action);
+  const int from = action / 100, to = action - 100 * (action / 100);
+  const int ply = __builtin_amdgcn_readfirstlane((int)hdr_u32(R, kOffPly));
+  const int battleless = __builtin_amdgcn_readfirstlane((int)hdr_u32(R, kOffBattleless));
+  const int ring_count = __builtin_amdgcn_readfirstlane((int)R[kOffRingCount]);
+  const int pt = __builtin_amdgcn_readfirstlane((int)R[kOffRing + 2 * ((ply - 1) & 31) + 1]);
+  const int p = ply & 1, o = 1 - p;
+  const int X = reg_at(q.id, from);
+  uint32_t wX = reg_at(q.w0, from);
+  const int T = reg_at(q.id, to);
+  uint32_t wT = T >= 0 ? reg_at(q.w0, to) : 0u;
+
+  // previous move: its mover A (the opponent's piece still on its destination a)
+  int A = -1, a = -1;
+  bool prev_threat = false;
+  if (ring_count > 0 && owned_by(reg_at(q.id, pt), o)) {
+    A = reg_at(q.id, pt);
+    a = pt;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int y = neighbour(a, k);
+      if (y >= 0 && owned_by(reg_at(q.id, y), p)) prev_threat = true;
+    }
+  }
+
+  // 1. active adjacency (pre-move): own movable pieces next to opponent
+  //    pieces, except the attack being made; the opponent's slot codes of the
+  //    neighbouring squares come from the registers of other lanes
+  {
+    int code[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) code[h] = owned_by(q.id[h], o) ? (slot10(q.w0[h]) & 15) : 15;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int x = lane + 64 * h;
+      uint32_t bits = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int y = x < kSquares ? neighbour(x, k) : -1;
+        const int src = y < 0 ? 0 : (y & 63);
+        const int c0 = __shfl(code[0], src, 64), c1 = __shfl(code[1], src, 64);
+        const int c = y < 0 ? 15 : y < 64 ? c0 : c1;
+        if (c < 11 && !(x == from && y == to)) bits |= 1u << c;
+      }
+      if (bits && owned_by(q.id[h], p) && movable_type(p_type(q.w0[h])))
+        atomicOr(&piece_words(R, q.id[h])[2], bits);
+    }
+  }
+
+  // 2-4. evasion, move or battle with reveals and death records
+  const bool battle = T >= 0;
+  uint32_t evade = 0;
+  if (A >= 0 && adjacent(from, a) && !battle && !adjacent(to, a)) {
+    const int sl = slot10(reg_at(q.w0, a));
+    if (sl >= 0) evade = (1u << sl) << 11;
+  }
+  int flag_winner = -1;
+  bool attacker_alive = true;
+  int res = 0;   // 0 attacker wins (or no battle), 1 defender wins, 2 tie (Table "pieces")
+  if (battle) {
+    const int ta = p_type(wX), td = p_type(wT);
+    const bool rY = p_revealed(wT);
+    if (td == kFlag) res = 0;
+    else if (td == kBomb) res = ta == kMiner ? 0 : 1;
+    else if (ta == kSpy && td == kMarshal) res = 0;
+    else res = ta > td ? 0 : ta < td ? 1 : 2;
+    wX |= 1u << 5;
+    wT |= 1u << 5;
+    if (td == kFlag) flag_winner = p;
+    const uint32_t clear = (1u << 4) | (7u << 7) | (127u << 10);
+    if (res == 0) {
+      wT = (wT & ~clear) | ((rY ? 4u : 6u) << 7) | ((uint32_t)to << 10);
+    } else if (res == 1) {
+      attacker_alive = false;
+      wX = (wX & ~clear) | ((rY ? 1u : 3u) << 7) | ((uint32_t)to << 10);
+    } else {
+      attacker_alive = false;
+      wX = (wX & ~clear) | ((rY ? 2u : 3u) << 7) | ((uint32_t)to << 10);
+      wT = (wT & ~clear) | ((rY ? 5u : 6u) << 7) | ((uint32_t)to << 10);
+    }
+  }
+  wX |= 1u << 6;                                   // moved
+  if (!adjacent(from, to)) wX |= 1u << 30;         // a long move: a known Scout
+  // 5. threats by the mover from its destination (the neighbours' words are
+  //    untouched by this move; `from`, now empty, held the mover)
+  uint32_t threat = 0;
+  if (attacker_alive) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int y = neighbour(to, k);
+      if (y < 0 || !owned_by(reg_at(q.id, y), o)) continue;
+      const int sl = slot10(reg_at(q.w0, y));
+      if (sl >= 0) threat |= 1u << sl;
+    }
+  }
+  // 6. protection: a non-battle reply to a threat that newly puts the mover
+  //    next to a square beside the threatener (the squares looked at are
+  //    neither `from` nor `to`, so their registers are current)
+  uint32_t prot2 = 0, prot3 = 0;
+  if (!battle && A >= 0 && prev_threat) {
+    const uint32_t bitA = 1u << slot13(reg_at(q.w0, a));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int sq = neighbour(a, k);
+      if (sq < 0 || is_lake_sq(sq)) continue;
+      if (!adjacent(sq, to) || sq == from || adjacent(sq, from)) continue;
+      const int oid = reg_at(q.id, sq);
+      if (owned_by(oid, p)) {
+        prot2 |= (1u << slot13(reg_at(q.w0, sq))) << 11;
+        prot3 |= bitA;
+        if (lane == 0) {
+          uint32_t* pb = piece_words(R, oid);
+          atomicOr(&pb[3], (1u << slot13(wX)) << 13);
+          atomicOr(&pb[0], bitA << 17);
+        }
+      } else if (oid == kEmpty) {
+        prot2 |= (1u << 11) << 11;
+        prot3 |= bitA;
+      }
+    }
+  }
+  // 7-8. record writes: board, pieces, ring and counters
+  const int to_id = !battle || res == 0 ? X : res == 2 ? kEmpty : T;
+  if (lane == 0) {
+    uint32_t* px = piece_words(R, X);
+    set_board(R, from, kEmpty);
+    set_board(R, to, to_id);
+    px[0] = wX;
+    if (battle) piece_words(R, T)[0] = wT;
+    if (evade | threat) atomicOr(&px[1], evade | threat);
+    if (prot2) atomicOr(&px[2], prot2);
+    if (prot3) atomicOr(&px[3], prot3);
+    const int slot = ply & 31;
+    R[kOffRing + 2 * slot] = (uint8_t)from;
+    R[kOffRing + 2 * slot + 1] = (uint8_t)to;
+    if (ring_count < 32) R[kOffRingCount] = (uint8_t)(ring_count + 1);
+    set_hdr_u32(R, kOffPly, (uint32_t)(ply + 1));
+    set_hdr_u32(R, kOffBattleless, battle ? 0u : (uint32_t)(battleless + 1));
+  }
+  // the registers of the two squares the move changed, then the terminal
+  // check (App. A; App. D.1)
+  const uint32_t to_w0 = to_id == X ? wX : to_id == T ? wT : 0u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int x = lane + 64 * h;
+    if (x == from) { q.id[h] = kEmpty; q.w0[h] = 0u; }
+    if (x == to) { q.id[h] = to_id; q.w0[h] = to_w0; }
+  }
+  FastOut out{0, 0, kReasonNone};
+  if (flag_winner >= 0) {
+    out = FastOut{1, flag_winner == 0 ? 1 : -1, kReasonFlag};
+  } else if (!fast_has_move(q, o)) {
+    out = fast_has_move(q, p) ? FastOut{1, p == 0 ? 1 : -1, kReasonForcedWin} : FastOut{1, 0, kReasonForcedDraw};
+  } else if ((battle ? 0 : battleless + 1) >= rules.k_battleless) {
+    out = FastOut{1, 0, kReasonKMove};
+  } else if (ply + 1 >= rules.max_moves) {
+    out = FastOut{1, 0, kReasonMaxMoves};
+  }
+  if (lane == 0) {
+    R[kOffDone] = (uint8_t)out.done;
+    R[kOffOutcome] = (uint8_t)(int8_t)out.outcome;
+    R[kOffReason] = (uint8_t)out.reason;
+  }
+  return out;
+}
+
+// reset_game for the fast path: a fresh setup is terminal only when a player
+// to move has no movable piece with room, checked on the registers.
+__device__ __forceinline__ void fast_reset_game(uint8_t* R, uint8_t* scratch, Rules rules, uint32_t game_id,
+                                                uint32_t episode, uint32_t redraws) {
+  for (int guard = 0;; ++guard) {
+    fresh_setup(R, scratch, rules.seed, game_id, episode, redraws);
+    SquareRegs q;
+    load_regs(R, q);
+    FastOut t{0, 0, kReasonNone};
+    if (!fast_has_move(q, 0)) t = fast_has_move(q, 1) ? FastOut{1, -1, kReasonForcedWin} : FastOut{1, 0, kReasonForcedDraw};
+    if (lane_id() == 0) {
+      R[kOffDone] = (uint8_t)t.done;
+      R[kOffOutcome] = (uint8_t)(int8_t)t.outcome;
+      R[kOffReason] = (uint8_t)t.reason;
+    }
+    wave_sync();
+    // a setup that is already terminal is replaced by the next episode's
+    // (probability ~4e-6 per game); the bound only guards against a hang
+    if (!(t.done && rules.auto_reset && guard < 1000)) break;
+    ++episode;
+    ++redraws;
+  }
+}
+
+// step_game for the fast path (drawn actions, no competitive-play rule).
+__device__ __forceinline__ StepOut fast_step_game(uint8_t* R, uint8_t* scratch, uint8_t* work, Rules rules,
+                                                  int action, SquareRegs& q) {
+  StepOut o{0, 0, 0, 0, false};
+  if (!R[kOffDone]) {
+    if (action == -1) return o;
+    const FastOut f = fast_apply(R, rules, action, q);
+    if (!f.done) return o;
+    wave_sync();
+  }
+  o.done = 1;
+  o.outcome = (int8_t)R[kOffOutcome];
+  o.reason = R[kOffReason];
+  o.ep_len = (int)hdr_u32(R, kOffPly);
+  (void)work;
+  if (rules.auto_reset)
+    fast_reset_game(R, scratch, rules, hdr_u32(R, kOffGameId), hdr_u32(R, kOffEpisode) + 1,
+                    hdr_u32(R, kOffRedraws));
   return o;
 }
 

@@ -96,9 +96,12 @@ __host__ __device__ __forceinline__ constexpr int ply_wave_lds_bytes(int enc, in
 }
 static_assert(kNoObsSlabBytes % 16 == 0, "record buffers stay 16-byte aligned");
 
-template <int MODE, int ENC>
+// FAST: the fused ply's register-board path (drawn actions, neither
+// competitive-play rule on); otherwise the general path.
+template <int MODE, int ENC, bool FAST = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone ? 5 : 4))) k_ply(PlyArgs a) {
+  static_assert(!FAST || MODE == (kDoMask | kDoSample | kDoEncode | kDoStep), "the fast path is the fused ply's");
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
   uint8_t* slab = smem + wave * ply_wave_lds_bytes(ENC, a.layout);
@@ -185,9 +188,28 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       uint8_t* gstate = a.states + (size_t)slot * kRecordBytes;
       const int oi = a.out_index ? a.out_index[i] : i;
       int action = -1;
+      SquareRegs rg;
       if (MODE & kDoMask) {
         uint64_t w[3];
-        const int n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
+        uint64_t d[4];
+        int n;
+        uint32_t pk[2];
+        if (FAST) {
+          // with a mask to write, the destination sets; else counts suffice
+          load_regs(R, rg);
+          const int p = (int)(hdr_u32(R, kOffPly) & 1);
+          const bool done = R[kOffDone] != 0;
+          if (a.mask) {
+            fast_dests(rg, p, done, d);
+            n = count_dests(d);
+            words_from_dests(d, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
+          } else {
+            dir_counts(rg, p, done, pk);
+            n = total_count(pk);
+          }
+        } else {
+          n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
+        }
         fetch_next();
         if (a.mask) {
           uint64_t* m = a.mask + (size_t)oi * kMaskWords;
@@ -196,7 +218,17 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
             if (lane + 64 * g < kMaskWords) m[lane + 64 * g] = w[g];
         }
         if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
-        if (MODE & kDoSample) {
+        if (FAST && (MODE & kDoSample)) {
+          const uint32_t gid = hdr_u32(R, kOffGameId), ply = hdr_u32(R, kOffPly), ep = hdr_u32(R, kOffEpisode);
+          const bool magnet = a.rules.sampler == kSamplerMagnet;
+          if (a.mask)
+            action = magnet ? (n == 0 ? -1 : sample_magnet(d[0], d[1], d[2], d[3], a.rules.seed, gid, ply, ep))
+                            : sample_dests(d, n, a.rules.seed, gid, ply, ep);
+          else
+            action = magnet ? (n == 0 ? -1 : magnet_counts(pk, a.rules.seed, gid, ply, ep))
+                            : sample_counts(pk, n, a.rules.seed, gid, ply, ep);
+          if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
+        } else if (MODE & kDoSample) {
           if (a.rules.sampler == kSamplerMagnet) {
             const uint64_t* ts = reinterpret_cast<const uint64_t*>(slab + kSlabImage);
             const bool second = lane + 64 < kSquares;
@@ -224,7 +256,9 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       }
       if (MODE & kDoStep) {
         if (a.hist) store_record(a.hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
-        StepOut o = step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, slab + kSlabProbQ, a.rules, action);
+        StepOut o = FAST ? fast_step_game(R, slab + kSlabScratch, slab + kSlabProbQ, a.rules, action, rg)
+                         : step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, slab + kSlabProbQ,
+                                                                    a.rules, action);
         if (lane == 0) {
           const size_t row = (size_t)a.out_base + oi;
           if (a.done) a.done[row] = (int8_t)o.done;
@@ -737,12 +771,21 @@ inline int waves_for(int G, int S, size_t max_lds) {
 // Dynamic LDS of one fused-engine workgroup.
 inline size_t lds_for(int G, int S, size_t max_lds) { return (size_t)waves_for(G, S, max_lds) * wave_lds_bytes(S); }
 
-const void* fused_kernel(int enc) {
+const void* fused_kernel(int enc, bool fast) {
+  if (fast)
+    return enc == 1 ? reinterpret_cast<const void*>(&k_ply<kFused, 1, true>)
+         : enc == 2 ? reinterpret_cast<const void*>(&k_ply<kFused, 2, true>)
+         : enc == kEncNone ? reinterpret_cast<const void*>(&k_ply<kFused, kEncNone, true>)
+                    : reinterpret_cast<const void*>(&k_ply<kFused, 0, true>);
   return enc == 1 ? reinterpret_cast<const void*>(&k_ply<kFused, 1>)
        : enc == 2 ? reinterpret_cast<const void*>(&k_ply<kFused, 2>)
        : enc == kEncNone ? reinterpret_cast<const void*>(&k_ply<kFused, kEncNone>)
                   : reinterpret_cast<const void*>(&k_ply<kFused, 0>);
 }
+
+// The fused ply takes the register-board path unless a competitive-play
+// rule is on.
+inline bool fast_rules(const Rules& r) { return !r.two_square && !r.chasing; }
 
 // grow: observation-free plies, where a game is short next to the loop's
 // fixed costs; the tile grows up to 8 games while every wave still gets two
@@ -759,7 +802,7 @@ int launch_ply(const DevLimits& d, hipStream_t s, int mode, PlyArgs a, int G, in
   const void* fn = nullptr;
   switch (mode) {
     case kFused:
-      fn = fused_kernel(enc);
+      fn = fused_kernel(enc, fast_rules(a.rules));
       break;
     case kDoMask: fn = reinterpret_cast<const void*>(&k_ply<kDoMask, 0>); break;
     case kDoEncode:
@@ -979,7 +1022,8 @@ static int init_context(const stratego_config* cfg, void* hip_stream, stratego_c
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int32_t*>(c->hist_clock), 2, 0);
   }
   // kernels whose dynamic LDS may exceed the default limit
-  const void* big_lds[] = {fused_kernel(0), fused_kernel(1), fused_kernel(2),
+  const void* big_lds[] = {fused_kernel(0, false), fused_kernel(1, false), fused_kernel(2, false),
+                           fused_kernel(0, true), fused_kernel(1, true), fused_kernel(2, true),
                            reinterpret_cast<const void*>(&k_ply<kDoEncode, 0>),
                            reinterpret_cast<const void*>(&k_ply<kDoEncode, 1>),
                            reinterpret_cast<const void*>(&k_ply<kDoEncode, 2>)};
@@ -1173,7 +1217,9 @@ int static_device(StaticDevice** out) {
     d.scratch = reinterpret_cast<unsigned int*>(ptr);
     d.lim = DevLimits{prop.multiProcessorCount, prop.sharedMemPerBlock};
     for (int enc = 0; enc < 3; ++enc)
-      (void)hipFuncSetAttribute(fused_kernel(enc), hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lim.max_lds);
+      for (int fast = 0; fast < 2; ++fast)
+        (void)hipFuncSetAttribute(fused_kernel(enc, fast != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)d.lim.max_lds);
   });
   *out = &d;
   return d.rc;
@@ -1496,7 +1542,7 @@ int stratego_autotune(stratego_ctx* c, uint8_t* obs, uint64_t* mask, int32_t pli
       const size_t lds = lds_for(G, S, c->max_lds);
       if (lds > c->max_lds) continue;
       int per_cu = 0;
-      const void* fused = fused_kernel(S == kLayoutBits ? 1 : S == kLayoutBits1 ? 2 : 0);
+      const void* fused = fused_kernel(S == kLayoutBits ? 1 : S == kLayoutBits1 ? 2 : 0, fast_rules(rules_of(c)));
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused, 64 * waves_for(G, S, c->max_lds), lds) !=
               hipSuccess ||
           per_cu <= 0)
