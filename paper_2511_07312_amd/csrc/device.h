@@ -142,6 +142,12 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// A value every lane holds alike (read from LDS, say), moved to a scalar
+// register so that the code using it runs on the scalar unit.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = lane_id();
 #pragma unroll
@@ -217,6 +223,10 @@ __device__ __forceinline__ int slot13(uint32_t w0) {
   return t == kBomb ? 10 : t;
 }
 
+// x / 10 for 0 <= x < 1024 by a 24-bit multiply (full rate, where the
+// compiler's division by a constant takes a quarter-rate 32-bit multiply)
+__device__ __forceinline__ int div10(int x) { return (int)(__umul24((uint32_t)x, 205u) >> 11); }
+
 __device__ __forceinline__ bool adjacent(int a, int b) {
   int ra = a / 10, ca = a - 10 * ra, rb = b / 10, cb = b - 10 * rb;
   int d = abs(ra - rb) + abs(ca - cb);
@@ -225,7 +235,7 @@ __device__ __forceinline__ bool adjacent(int a, int b) {
 
 // orthogonal on-board neighbour k (0 up, 1 down, 2 left, 3 right) or -1
 __device__ __forceinline__ int neighbour(int s, int k) {
-  int r = s / 10, c = s - 10 * r;
+  int r = div10(s), c = s - 10 * r;
   switch (k) {
     case 0: return r < 9 ? s + 10 : -1;
     case 1: return r > 0 ? s - 10 : -1;
@@ -1117,14 +1127,16 @@ __device__ __forceinline__ void load_regs(const uint8_t* R, SquareRegs& q) {
   q.id[1] = lane < kSquares - 64 ? board_at(R, 64 + lane) : kLake;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int t = lane + 64 * h;   // column-major index: column t / 10, row t % 10
-    q.tid[h] = t < kSquares ? board_at(R, 10 * (t % 10) + t / 10) : kLake;
+    // column-major index t: column t / 10, row t % 10
+    const int t = lane + 64 * h, tc = div10(t);
+    q.tid[h] = t < kSquares ? board_at(R, 10 * (t - 10 * tc) + tc) : kLake;
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) q.w0[h] = q.id[h] >= 0 ? piece_words(R, q.id[h])[0] : 0u;
 }
 
-__device__ __forceinline__ bool owned_by(int id, int p) { return id >= 0 && owner(id) == p; }
+// id names a piece of player p (ids 40p .. 40p + 39); false for -1 and -2
+__device__ __forceinline__ bool owned_by(int id, int p) { return (unsigned)(id - 40 * p) < 40u; }
 
 // Squares holding player p's pieces, and the empty squares.
 __device__ __forceinline__ Set100 occupied(const SquareRegs& q, int p) {
@@ -1147,6 +1159,27 @@ __device__ __forceinline__ uint32_t reg_at(const uint32_t v[2], int y) {
 __device__ __forceinline__ uint64_t s_window(Set100 v, int s) {
   if (s >= 64) return v.hi >> (s - 64);
   return s == 0 ? v.lo : (v.lo >> s) | (v.hi << (64 - s));
+}
+
+// The 10 squares of a row (s = 10 * row) or, in a transposed set, of a column
+// (s = 10 * column), as bits 0-9.
+__device__ __forceinline__ uint32_t line10(Set100 v, int s) { return (uint32_t)s_window(v, s) & 1023u; }
+
+// Moves of a Scout at position i of a 10-square line towards higher
+// positions: the run of open squares after i, plus one if the square that
+// ends it is a stop (an enemy) square; the line's end stops the run, since
+// positions past 9 read as closed and as no stop.
+__device__ __forceinline__ uint32_t line_up(uint32_t open, uint32_t stop, int i) {
+  const int run = __builtin_ctz(~(open >> (i + 1)));
+  return (uint32_t)run + ((stop >> (i + 1 + run)) & 1u);
+}
+// The same towards lower positions: bits i-1 .. 0 are moved to the top of the
+// word, where the run is counted from bit 31 down.
+__device__ __forceinline__ uint32_t line_down(uint32_t open, uint32_t stop, int i) {
+  const uint32_t top = (open << 1) << (31 - i);   // bit i-1 to bit 31; nothing for i = 0
+  const int run = __builtin_clz(~top);             // at most i: the low 32 - i bits of ~top are set
+  const int below = i - 1 - run;                   // the square that ends the run
+  return (uint32_t)run + (below >= 0 ? (stop >> (below & 31)) & 1u : 0u);
 }
 
 // Length of the run of squares of `open` going up from index i + 1 (at most
@@ -1226,24 +1259,26 @@ __device__ __forceinline__ void dir_counts(const SquareRegs& q, int p, bool done
   for (int h = 0; h < 2; ++h) {
     const int t = p_type(q.w0[h]);
     const bool mine = !done && owned_by(q.id[h], p) && movable_type(t);
-    auto bit = [&](Set100 v) { return (uint32_t)(((h == 0 ? v.lo : v.hi) >> lane) & 1ull); };
-    pk[h] = mine ? bit(dn) | bit(lf) << 4 | bit(rt) << 8 | bit(up) << 12 : 0u;
+    // the lane's own bit of a wave-uniform mask (a v_cndmask on the mask)
+    auto bit = [&](Set100 v, uint32_t one) {
+      return __builtin_amdgcn_inverse_ballot_w64(h == 0 ? v.lo : v.hi) ? one : 0u;
+    };
+    pk[h] = mine ? bit(dn, 1u) + bit(lf, 1u << 4) + bit(rt, 1u << 8) + bit(up, 1u << 12) : 0u;
     scout |= mine && t == kScout;
   }
   if (ballot(scout) == 0) return;
   const Set100 empty_t = ballot100(q.tid[0] == kEmpty, q.tid[1] == kEmpty);
   const Set100 target_t = s_or(empty_t, ballot100(owned_by(q.tid[0], 1 - p), owned_by(q.tid[1], 1 - p)));
+  const int l = lane_here();
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (done || !owned_by(q.id[h], p) || p_type(q.w0[h]) != kScout) continue;
-    const int x = lane + 64 * h, r = x / 10, c = x - 10 * r, xt = 10 * c + r;
-    int cap;
-    uint32_t v = 0;
-    v |= (uint32_t)(run_down(empty_t, target_t, xt, r, cap) + cap);
-    v |= (uint32_t)(run_down(empty, target, x, c, cap) + cap) << 4;
-    v |= (uint32_t)(run_up(empty, target, x, 9 - c, cap) + cap) << 8;
-    v |= (uint32_t)(run_up(empty_t, target_t, xt, 9 - r, cap) + cap) << 12;
-    pk[h] = v;
+    const int x = l + 64 * h, r = div10(x), c = x - 10 * r;
+    // the Scout's row and column as 10-bit lines, position c resp. r
+    const uint32_t row_e = line10(empty, 10 * r), row_t = line10(target, 10 * r);
+    const uint32_t col_e = line10(empty_t, 10 * c), col_t = line10(target_t, 10 * c);
+    pk[h] = line_down(col_e, col_t, r) | line_down(row_e, row_t, c) << 4 | line_up(row_e, row_t, c) << 8 |
+            line_up(col_e, col_t, r) << 12;
   }
 }
 
@@ -1405,12 +1440,18 @@ __device__ __forceinline__ FastOut fast_apply(uint8_t* R, Rules rules, int actio
   }
 
   // 1. active adjacency (pre-move): own movable pieces next to opponent
-  //    pieces, except the attack being made; the opponent's slot codes of the
-  //    neighbouring squares come from the registers of other lanes
+  //    pieces, except the attack being made.  Each square's opponent slot
+  //    bit (1 << slot10, 0 without such a piece) is packed with the other
+  //    half's into one register (square lane in bits 0-15, square 64 + lane
+  //    in bits 16-31), so one lane permute fetches a neighbour of either half.
   {
-    int code[2];
+    uint32_t ebit[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) code[h] = owned_by(q.id[h], o) ? (slot10(q.w0[h]) & 15) : 15;
+    for (int h = 0; h < 2; ++h) {
+      const int sl = slot10(q.w0[h]);
+      ebit[h] = owned_by(q.id[h], o) && sl >= 0 ? 1u << (sl & 15) : 0u;
+    }
+    const int packed = (int)(ebit[0] | ebit[1] << 16);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int x = lane + 64 * h;
@@ -1418,10 +1459,9 @@ __device__ __forceinline__ FastOut fast_apply(uint8_t* R, Rules rules, int actio
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int y = x < kSquares ? neighbour(x, k) : -1;
-        const int src = y < 0 ? 0 : (y & 63);
-        const int c0 = __shfl(code[0], src, 64), c1 = __shfl(code[1], src, 64);
-        const int c = y < 0 ? 15 : y < 64 ? c0 : c1;
-        if (c < 11 && !(x == from && y == to)) bits |= 1u << c;
+        const uint32_t g = (uint32_t)__shfl(packed, y & 63, 64);
+        const uint32_t v = (y >= 64 ? g >> 16 : g) & 0x7FFu;
+        bits |= y >= 0 && !(x == from && y == to) ? v : 0u;
       }
       if (bits && owned_by(q.id[h], p) && movable_type(p_type(q.w0[h])))
         atomicOr(&piece_words(R, q.id[h])[2], bits);

@@ -97,11 +97,13 @@ __host__ __device__ __forceinline__ constexpr int ply_wave_lds_bytes(int enc, in
 static_assert(kNoObsSlabBytes % 16 == 0, "record buffers stay 16-byte aligned");
 
 // FAST: the fused ply's register-board path (drawn actions, neither
-// competitive-play rule on); otherwise the general path.
-template <int MODE, int ENC, bool FAST = false>
+// competitive-play rule on); otherwise the general path.  NOMASK: no mask
+// output (a.mask is NULL), so the ply samples from move counts alone.
+template <int MODE, int ENC, bool FAST = false, bool NOMASK = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone ? 5 : 4))) k_ply(PlyArgs a) {
   static_assert(!FAST || MODE == (kDoMask | kDoSample | kDoEncode | kDoStep), "the fast path is the fused ply's");
+  static_assert(FAST || !NOMASK, "the mask-free variant is a fast-path one");
   extern __shared__ __align__(16) uint8_t smem[];
   const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
   uint8_t* slab = smem + wave * ply_wave_lds_bytes(ENC, a.layout);
@@ -197,9 +199,9 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
         if (FAST) {
           // with a mask to write, the destination sets; else counts suffice
           load_regs(R, rg);
-          const int p = (int)(hdr_u32(R, kOffPly) & 1);
-          const bool done = R[kOffDone] != 0;
-          if (a.mask) {
+          const int p = (int)(uniform_u32(hdr_u32(R, kOffPly)) & 1);
+          const bool done = uniform_u32(R[kOffDone]) != 0;
+          if (!NOMASK && a.mask) {
             fast_dests(rg, p, done, d);
             n = count_dests(d);
             words_from_dests(d, reinterpret_cast<uint64_t*>(slab + kSlabImage), w);
@@ -211,7 +213,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
           n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
         }
         fetch_next();
-        if (a.mask) {
+        if (!NOMASK && a.mask) {
           uint64_t* m = a.mask + (size_t)oi * kMaskWords;
 #pragma unroll
           for (int g = 0; g < 3; ++g)
@@ -219,9 +221,12 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
         }
         if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
         if (FAST && (MODE & kDoSample)) {
-          const uint32_t gid = hdr_u32(R, kOffGameId), ply = hdr_u32(R, kOffPly), ep = hdr_u32(R, kOffEpisode);
+          // wave-uniform copies, so that the generator and the selection run
+          // on the scalar unit
+          const uint32_t gid = uniform_u32(hdr_u32(R, kOffGameId)), ply = uniform_u32(hdr_u32(R, kOffPly)),
+                         ep = uniform_u32(hdr_u32(R, kOffEpisode));
           const bool magnet = a.rules.sampler == kSamplerMagnet;
-          if (a.mask)
+          if (!NOMASK && a.mask)
             action = magnet ? (n == 0 ? -1 : sample_magnet(d[0], d[1], d[2], d[3], a.rules.seed, gid, ply, ep))
                             : sample_dests(d, n, a.rules.seed, gid, ply, ep);
           else
@@ -771,7 +776,8 @@ inline int waves_for(int G, int S, size_t max_lds) {
 // Dynamic LDS of one fused-engine workgroup.
 inline size_t lds_for(int G, int S, size_t max_lds) { return (size_t)waves_for(G, S, max_lds) * wave_lds_bytes(S); }
 
-const void* fused_kernel(int enc, bool fast) {
+const void* fused_kernel(int enc, bool fast, bool nomask = false) {
+  if (fast && nomask && enc == kEncNone) return reinterpret_cast<const void*>(&k_ply<kFused, kEncNone, true, true>);
   if (fast)
     return enc == 1 ? reinterpret_cast<const void*>(&k_ply<kFused, 1, true>)
          : enc == 2 ? reinterpret_cast<const void*>(&k_ply<kFused, 2, true>)
@@ -802,7 +808,7 @@ int launch_ply(const DevLimits& d, hipStream_t s, int mode, PlyArgs a, int G, in
   const void* fn = nullptr;
   switch (mode) {
     case kFused:
-      fn = fused_kernel(enc, fast_rules(a.rules));
+      fn = fused_kernel(enc, fast_rules(a.rules), a.mask == nullptr);
       break;
     case kDoMask: fn = reinterpret_cast<const void*>(&k_ply<kDoMask, 0>); break;
     case kDoEncode:
