@@ -79,13 +79,14 @@ __host__ __device__ __forceinline__ constexpr int wave_lds_bytes(int layout) { r
 // 2 bit planes of one observer at a time (layout 7), 3 no observations: plies
 // that only mask, sample and step (rollouts, recording plies).  Those need
 // only the record, the work areas and the to-square sets (4.9 KB of LDS per
-// wave with the spare record), so a CU holds 20 of their waves (5 per SIMD,
-// 96 VGPRs with a few spilled) instead of the 8 the both-observer encoder
-// allows.  Register budgets: the both-observer encoder is LDS-bound at 2
-// waves per SIMD anyway, so it may use 256 VGPRs; the one-observer encoder
-// runs best at 3 (168 VGPRs, no spills; 4% faster than 4 waves with 128 and
-// spills); the observation-free variant at 5 (5% faster than 4 waves with
-// 128 VGPRs; 6 and 8 waves spill too much); the byte-image layouts at 4.
+// wave with the spare record), so a CU holds 32 of their waves instead of the
+// 8 the both-observer encoder allows.  Register budgets: the both-observer
+// encoder is LDS-bound at 2 waves per SIMD anyway, so it may use 256 VGPRs;
+// the one-observer encoder runs best at 3 (168 VGPRs, no spills; 4% faster
+// than 4 waves with 128 and spills); the observation-free register-board
+// variant without a mask output at 8 (64 VGPRs, no spills; 3% faster than 7),
+// the other observation-free ones at 5 (96 VGPRs, the general one with a few
+// spilled); the byte-image layouts at 4.
 constexpr int kEncNone = 3;
 constexpr int kNoObsSlabBytes = kSlabImage + kDestSetBytes;
 __host__ __device__ __forceinline__ constexpr int ply_slab_bytes(int enc, int layout) {
@@ -101,7 +102,7 @@ static_assert(kNoObsSlabBytes % 16 == 0, "record buffers stay 16-byte aligned");
 // output (a.mask is NULL), so the ply samples from move counts alone.
 template <int MODE, int ENC, bool FAST = false, bool NOMASK = false>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone ? 5 : 4))) k_ply(PlyArgs a) {
+__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone ? (FAST && NOMASK ? 8 : 5) : 4))) k_ply(PlyArgs a) {
   static_assert(!FAST || MODE == (kDoMask | kDoSample | kDoEncode | kDoStep), "the fast path is the fused ply's");
   static_assert(FAST || !NOMASK, "the mask-free variant is a fast-path one");
   extern __shared__ __align__(16) uint8_t smem[];
@@ -121,7 +122,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   // of its own.  With a ticket counter (persistent plies with observations) a
   // wave takes the next tile in address order whenever it becomes free;
   // otherwise wave w of workgroup b takes tiles bW+w, bW+w+gridDim.x*W, ...
-  const bool dynamic = a.tickets != nullptr;
+  const bool dynamic = ENC != kEncNone && a.tickets != nullptr;   // plies without observations split statically
   const int workers = gridDim.x * W;
   auto grab = [&]() -> int {
     int t = 0;
