@@ -84,9 +84,10 @@ __host__ __device__ __forceinline__ constexpr int wave_lds_bytes(int layout) { r
 // encoder is LDS-bound at 2 waves per SIMD anyway, so it may use 256 VGPRs;
 // the one-observer encoder runs best at 3 (168 VGPRs, no spills; 4% faster
 // than 4 waves with 128 and spills); the observation-free register-board
-// variant without a mask output at 8 (64 VGPRs, no spills; 3% faster than 7),
-// the other observation-free ones at 5 (96 VGPRs, the general one with a few
-// spilled); the byte-image layouts at 4.
+// variant without a mask output at 7 (72 VGPRs, no spills; 3% faster than 8
+// waves with 64 VGPRs and a few spilled), the other observation-free ones at
+// 5 (96 VGPRs, the general one with a few spilled); the byte-image layouts
+// at 4.
 constexpr int kEncNone = 3;
 constexpr int kNoObsSlabBytes = kSlabImage + kDestSetBytes;
 __host__ __device__ __forceinline__ constexpr int ply_slab_bytes(int enc, int layout) {
@@ -102,7 +103,7 @@ static_assert(kNoObsSlabBytes % 16 == 0, "record buffers stay 16-byte aligned");
 // output (a.mask is NULL), so the ply samples from move counts alone.
 template <int MODE, int ENC, bool FAST = false, bool NOMASK = false>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone ? (FAST && NOMASK ? 8 : 5) : 4))) k_ply(PlyArgs a) {
+__attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone ? (FAST && NOMASK ? 7 : 5) : 4))) k_ply(PlyArgs a) {
   static_assert(!FAST || MODE == (kDoMask | kDoSample | kDoEncode | kDoStep), "the fast path is the fused ply's");
   static_assert(FAST || !NOMASK, "the mask-free variant is a fast-path one");
   extern __shared__ __align__(16) uint8_t smem[];
@@ -137,6 +138,25 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   bool slot_ok = have && slot >= 0 && slot < a.total;
   if (slot_ok) load_record(slab, a.states + (size_t)slot * kRecordBytes);
   int cur = 0;   // offset of the current record buffer: 0 or spare
+  // Plies without observations write a game's results and record back only
+  // after the next game's record has been requested: one counter tracks
+  // loads and stores in issue order, so waiting for that load then does not
+  // wait for these stores too.  The pending record is in the other buffer.
+  constexpr bool kDefer = ENC == kEncNone && (MODE & kDoStep) != 0;
+  uint8_t* pend_g = nullptr;    // where the pending record goes (NULL: none)
+  size_t pend_row = 0;
+  StepOut pend_o{0, 0, 0, 0, false};
+  auto flush = [&]() {
+    if (!kDefer || pend_g == nullptr) return;
+    if (lane == 0) {
+      if (a.done) a.done[pend_row] = (int8_t)pend_o.done;
+      if (a.outcome) a.outcome[pend_row] = (int8_t)pend_o.outcome;
+      if (a.reason) a.reason[pend_row] = (uint8_t)pend_o.reason;
+      if (a.ep_len) a.ep_len[pend_row] = (int16_t)pend_o.ep_len;
+    }
+    store_record(pend_g, slab + (spare - cur));
+    pend_g = nullptr;
+  };
   while (have) {
     // the next game of this wave (its chunk is grabbed only when needed)
     int ngi = gi + 1, ntile = tile;
@@ -172,6 +192,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
         if (lane < 32) p1 = src[64 + lane];
       }
       fetched = true;
+      flush();   // the previous game's write-back, behind this load
     };
     bool parked = false;
     auto park_next = [&]() {
@@ -265,17 +286,25 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
         StepOut o = FAST ? fast_step_game(R, slab + kSlabScratch, slab + kSlabProbQ, a.rules, action, rg)
                          : step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, slab + kSlabProbQ,
                                                                     a.rules, action);
+        const size_t row = (size_t)a.out_base + oi;
         if (lane == 0) {
-          const size_t row = (size_t)a.out_base + oi;
-          if (a.done) a.done[row] = (int8_t)o.done;
-          if (a.outcome) a.outcome[row] = (int8_t)o.outcome;
-          if (a.reason) a.reason[row] = (uint8_t)o.reason;
-          if (a.ep_len) a.ep_len[row] = (int16_t)o.ep_len;
+          if (!kDefer) {
+            if (a.done) a.done[row] = (int8_t)o.done;
+            if (a.outcome) a.outcome[row] = (int8_t)o.outcome;
+            if (a.reason) a.reason[row] = (uint8_t)o.reason;
+            if (a.ep_len) a.ep_len[row] = (int16_t)o.ep_len;
+          }
           if (o.illegal) atomicMin(&a.err[0], slot);
           if (a.hist) a.hist_steps[hist_row + slot] = pack_step(action, o);
         }
         wave_sync();
-        store_record(gstate, R);
+        if (kDefer) {
+          pend_g = gstate;
+          pend_row = row;
+          pend_o = o;
+        } else {
+          store_record(gstate, R);
+        }
       }
     }
     resolve_next();
@@ -288,6 +317,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     have = next_have;
     cur = spare - cur;
   }
+  flush();
   if (a.ts) {
     __syncthreads();
     if (threadIdx.x == 0) atomicMax(&a.ts[1], (unsigned long long)wall_clock64());
