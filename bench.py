@@ -146,6 +146,7 @@ def serving_bench(E, torch, n_requests=240, seed=4):
 
     st, _ = run(None)
     sat = st["game_steps"] / st["wall_s"]
+    sat_idle = 1.0 - st["gpu_busy_s"] / st["gpu_span_s"] if st["gpu_span_s"] > 0 else None
     mean_work = float((sizes * plies).mean())
     out_rates = []
     for f in (0.3, 0.6, 0.9):
@@ -155,11 +156,13 @@ def serving_bench(E, torch, n_requests=240, seed=4):
             load=f, requests_per_s=rate, throughput=st["game_steps"] / st["wall_s"],
             step_p50_ms=percentile(lat[0], 0.5), step_p99_ms=percentile(lat[0], 0.99),
             rollout_p50_ms=percentile(lat[1], 0.5), rollout_p99_ms=percentile(lat[1], 0.99),
+            gpu_idle_fraction=1.0 - st["gpu_busy_s"] / st["gpu_span_s"] if st["gpu_span_s"] > 0 else None,
             iterations=st["iterations"], peak_active_games=st["peak_active_games"]))
         print(f"[bench] serving at {f:.1f}x: {out_rates[-1]}", file=sys.stderr, flush=True)
     assert eng.error() == (0, -1)
     eng.close()
-    return dict(unit="game steps/s", saturated=sat, requests=n_requests, games=total,
+    return dict(unit="game steps/s", saturated=sat, saturated_gpu_idle_fraction=sat_idle,
+                requests=n_requests, games=total,
                 pool_slots=slots, rates=out_rates)
 
 

@@ -244,16 +244,22 @@ int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int3
  * soon as they have arrived (realtime = 1: at arrival_s seconds after the call
  * starts; realtime = 0: all at once) and both enough free slots and enough of
  * the memory budget remain (a game reserves 1536 bytes, plus its observation
- * bytes, 97600 or 48800, for step requests); mem_budget_bytes <= 0 uses the device's free memory at the start
- * of the call.  Every iteration runs one fused ply over all admitted games, so
- * requests that arrive while others run join them on the device; a request
- * leaves after its last ply, when its final records are copied to rows
- * [first, first + num_games) of out_states_dev.  results[r] receives admission
- * and completion times.  Each game's result depends only on its record, so it
- * is the same alone and in any mix.  The error word latches E_BAD_STATE for a
- * malformed input record (that game then runs from whatever its slot held).
- * Synchronises the stream.  Errors: E_INVAL (bad request, a request that can
- * never fit, step requests without obs_out_dev), E_HIP. */
+ * bytes, 97600 or 48800, for step requests); mem_budget_bytes <= 0 uses the
+ * device's free memory at the start of the call.  Every iteration runs one
+ * fused ply over all admitted games, so requests that arrive while others run
+ * join them on the device; a request leaves after its last ply, when its
+ * final records are copied to rows [first, first + num_games) of
+ * out_states_dev.  The host enqueues an iteration while the previous one runs
+ * (two in flight), and imports admitted records on a second stream of the
+ * context beside them; a request's slots are reused once the iteration that
+ * copied it out has completed.  results[r] receives the host time of
+ * admission and the time the device completed the request's last iteration
+ * (device event time placed on the host clock).  Each game's result depends
+ * only on its record, so it is the same alone and in any mix.  The error word
+ * latches E_BAD_STATE for a malformed input record (that game then runs from
+ * whatever its slot held).  Synchronises the stream.  Errors: E_INVAL (bad
+ * request, a request that can never fit, step requests without obs_out_dev),
+ * E_HIP. */
 #define STRATEGO_REQ_STEP 0
 #define STRATEGO_REQ_ROLLOUT 1
 typedef struct {
@@ -268,12 +274,15 @@ typedef struct {
   double done_s;
 } stratego_request_result;
 typedef struct {
-  double wall_s;
+  double wall_s;                /* host time of the whole call */
   int64_t game_steps;
   int32_t iterations;
   int32_t peak_active_games;
   int64_t peak_reserved_bytes;
   int64_t budget_bytes;
+  double gpu_busy_s;            /* device time inside iterations (their plies and copies out) */
+  double gpu_span_s;            /* device time from the first iteration's start to the last one's end;
+                                   1 - busy / span is the share the device idled between iterations */
 } stratego_serve_stats;
 int stratego_serve(stratego_ctx* ctx, const stratego_request* reqs, int32_t nreq,
                    const void* in_states_dev, void* out_states_dev, uint8_t* obs_out_dev,

@@ -754,7 +754,8 @@ struct stratego_ctx {
   int32_t* err;
   unsigned long long* ts;
   unsigned int* tickets;   // per-ply work counters of the persistent fused kernel
-  int32_t* srv_dev;    // serving slot lists, 4 x N
+  hipStream_t copy_stream;   // serving: record imports beside the plies (default priority)
+  int32_t* srv_dev;    // serving slot lists, 2 sets (one per iteration in flight) of 4 x N
   int32_t* srv_host;   // pinned host staging of the same lists
   int64_t steps;
   int G, S;
@@ -1031,7 +1032,14 @@ static int init_context(const stratego_config* cfg, void* hip_stream, stratego_c
     stratego_destroy(c);
     return STRATEGO_E_NOMEM;
   }
-  const size_t lists = 4 * (size_t)cfg->num_games * sizeof(int32_t);
+  if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->copy_stream = nullptr;
+    c->srv_dev = nullptr;
+    c->srv_host = nullptr;
+    stratego_destroy(c);
+    return STRATEGO_E_HIP;
+  }
+  const size_t lists = 8 * (size_t)cfg->num_games * sizeof(int32_t);
   if (hipMalloc(&c->srv_dev, lists) != hipSuccess) {
     c->srv_dev = nullptr;
     c->srv_host = nullptr;
@@ -1365,6 +1373,7 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
   if (c->hist) return STRATEGO_E_INVAL;   // the rollout buffer indexes whole-batch plies
   const int N = c->cfg.num_games;
   bool any_step = false;
+  int64_t total_games = 0;
   for (int r = 0; r < nreq; ++r) {
     const stratego_request& q = reqs[r];
     if ((q.kind != STRATEGO_REQ_STEP && q.kind != STRATEGO_REQ_ROLLOUT) || q.num_games < 1 ||
@@ -1372,6 +1381,7 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
         (q.kind == STRATEGO_REQ_STEP && q.plies != 1))
       return STRATEGO_E_INVAL;
     any_step |= q.kind == STRATEGO_REQ_STEP;
+    total_games += q.num_games;
   }
   if (any_step && !obs_out) return STRATEGO_E_INVAL;
   int64_t budget = mem_budget;
@@ -1387,148 +1397,218 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
   for (int r = 0; r < nreq; ++r)
     if (bytes_of(reqs[r]) > budget) return STRATEGO_E_INVAL;   // could never be admitted
 
-  // admission in arrival order (first come, first served)
+  // Everything the loop uses is allocated here, once per call.  Up to two
+  // iterations are in flight: iteration k is enqueued while k - 1 runs, and
+  // its host-side lists use buffer set k & 1, which iteration k - 2 (waited
+  // for first) used last.  A request's slots are free again once the
+  // iteration that copied its records out has completed; new requests are
+  // imported only into such slots, on the copy stream, so the imports
+  // overlap the plies in flight and the next iteration waits for them.
   std::vector<int> order(nreq);
   for (int r = 0; r < nreq; ++r) order[r] = r;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
-  std::vector<int32_t> free_slots(N);
-  for (int i = 0; i < N; ++i) free_slots[i] = N - 1 - i;
-  struct Active { int req; int remaining; std::vector<int32_t> slots; };
-  std::vector<Active> active;
-  int32_t* h_adm = c->srv_host;
-  int32_t* h_step = c->srv_host + N;
-  int32_t* h_roll = c->srv_host + 2 * (size_t)N;
-  int32_t* h_oidx = c->srv_host + 3 * (size_t)N;
-  int32_t* d_adm = c->srv_dev;
-  int32_t* d_step = c->srv_dev + N;
-  int32_t* d_roll = c->srv_dev + 2 * (size_t)N;
-  int32_t* d_oidx = c->srv_dev + 3 * (size_t)N;
+  std::vector<int32_t> slot_store((size_t)total_games);   // slots of request r from seg[r]
+  std::vector<int64_t> seg(nreq, 0);
+  std::vector<int32_t> remaining(nreq, 0), adm_off(nreq, 0), run_off(nreq, 0);
+  std::vector<int> active, admitted, finishing[2];
+  active.reserve(nreq);
+  admitted.reserve(nreq);
+  finishing[0].reserve(nreq);
+  finishing[1].reserve(nreq);
+  std::vector<int32_t> free_now, pend_free[2];
+  free_now.reserve(N);
+  pend_free[0].reserve(N);
+  pend_free[1].reserve(N);
+  for (int i = 0; i < N; ++i) free_now.push_back(N - 1 - i);
+  int32_t *h_adm[2], *h_step[2], *h_roll[2], *h_oidx[2], *d_adm[2], *d_step[2], *d_roll[2], *d_oidx[2];
+  for (int b = 0; b < 2; ++b) {
+    int32_t* hb = c->srv_host + (size_t)b * 4 * N;
+    int32_t* db = c->srv_dev + (size_t)b * 4 * N;
+    h_adm[b] = hb; h_step[b] = hb + N; h_roll[b] = hb + 2 * (size_t)N; h_oidx[b] = hb + 3 * (size_t)N;
+    d_adm[b] = db; d_step[b] = db + N; d_roll[b] = db + 2 * (size_t)N; d_oidx[b] = db + 3 * (size_t)N;
+  }
+  hipEvent_t ev_ref = nullptr, ev_first = nullptr, ev_start[2] = {}, ev_end[2] = {}, ev_import[2] = {};
+  bool ev_ok = hipEventCreate(&ev_ref) == hipSuccess && hipEventCreate(&ev_first) == hipSuccess;
+  for (int b = 0; b < 2; ++b)
+    ev_ok = ev_ok && hipEventCreate(&ev_start[b]) == hipSuccess && hipEventCreate(&ev_end[b]) == hipSuccess &&
+            hipEventCreateWithFlags(&ev_import[b], hipEventDisableTiming) == hipSuccess;
+  auto destroy_events = [&]() {
+    for (hipEvent_t e : {ev_ref, ev_first, ev_start[0], ev_start[1], ev_end[0], ev_end[1], ev_import[0], ev_import[1]})
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (!ev_ok) { destroy_events(); return STRATEGO_E_HIP; }
+
   const uint8_t* in = reinterpret_cast<const uint8_t*>(in_states);
   uint8_t* out = reinterpret_cast<uint8_t*>(out_states);
-  int64_t reserved = 0, game_steps = 0, peak_reserved = 0;
-  int next = 0, completed = 0, iterations = 0, peak_active = 0, active_games = 0;
+  int64_t reserved = 0, game_steps = 0, peak_reserved = 0, seg_next = 0;
+  int next = 0, completed = 0, iterations = 0, peak_active = 0, active_games = 0, inflight = 0;
+  int64_t k = 0;
+  double busy_ms = 0.0, last_end_ms = 0.0, first_ms = 0.0;
   const auto t0 = std::chrono::steady_clock::now();
   auto now_s = [&]() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   };
-  while (completed < nreq) {
-    // 1. admit arrived requests while slots and memory allow
-    double t = now_s();
+  // device time reference: completion times are the iterations' end events
+  // on the device clock, placed on the host clock by this event
+  if (hipEventRecord(ev_ref, c->stream) != hipSuccess || hipEventSynchronize(ev_ref) != hipSuccess) {
+    destroy_events();
+    return STRATEGO_E_HIP;
+  }
+  const double t_ref = now_s();
+  int rc = STRATEGO_OK;
+  // wait for the oldest iteration in flight and settle its requests
+  auto retire = [&]() {
+    const int b = (int)((k - inflight) & 1);
+    if (hipEventSynchronize(ev_end[b]) != hipSuccess) { rc = STRATEGO_E_HIP; return; }
+    float ms_busy = 0.f, ms_end = 0.f;
+    (void)hipEventElapsedTime(&ms_busy, ev_start[b], ev_end[b]);
+    (void)hipEventElapsedTime(&ms_end, ev_ref, ev_end[b]);
+    busy_ms += ms_busy;
+    last_end_ms = ms_end;
+    const double t_done = t_ref + ms_end / 1e3;
+    for (int r : finishing[b]) results[r].done_s = t_done;
+    completed += (int)finishing[b].size();
+    finishing[b].clear();
+    for (int32_t sl : pend_free[b]) free_now.push_back(sl);
+    pend_free[b].clear();
+    --inflight;
+  };
+  while (rc == STRATEGO_OK && completed < nreq) {
+    const int b = (int)(k & 1);
+    if (inflight == 2) { retire(); if (rc != STRATEGO_OK) break; }
+    // 1. admit arrived requests, first come first served, while free slots
+    //    and the memory budget allow
+    const double t = now_s();
     int nadm = 0;
-    std::vector<int> admitted;
+    admitted.clear();
     while (next < nreq) {
-      const stratego_request& q = reqs[order[next]];
+      const int r = order[next];
+      const stratego_request& q = reqs[r];
       if (realtime && q.arrival_s > t) break;
-      if ((int)free_slots.size() < q.num_games || reserved + bytes_of(q) > budget) break;
-      Active a;
-      a.req = order[next];
-      a.remaining = q.plies;
-      a.slots.resize(q.num_games);
+      if ((int)free_now.size() < q.num_games || reserved + bytes_of(q) > budget) break;
+      seg[r] = seg_next;
+      seg_next += q.num_games;
+      adm_off[r] = nadm;
       for (int j = 0; j < q.num_games; ++j) {
-        a.slots[j] = free_slots.back();
-        free_slots.pop_back();
-        h_adm[nadm + j] = a.slots[j];
+        const int32_t sl = free_now.back();
+        free_now.pop_back();
+        slot_store[(size_t)seg[r] + j] = sl;
+        h_adm[b][nadm + j] = sl;
       }
-      admitted.push_back(nadm);
       nadm += q.num_games;
       reserved += bytes_of(q);
       active_games += q.num_games;
-      results[a.req].admit_s = t;
-      active.push_back(std::move(a));
+      remaining[r] = q.plies;
+      results[r].admit_s = t;
+      active.push_back(r);
+      admitted.push_back(r);
       ++next;
     }
     peak_reserved = std::max(peak_reserved, reserved);
     peak_active = std::max(peak_active, active_games);
     if (active.empty()) {
-      if (next < nreq) {   // idle until the next arrival
+      if (inflight > 0) { retire(); continue; }   // completions free slots
+      if (next < nreq) {                           // idle until the next arrival
         const double wait = reqs[order[next]].arrival_s - now_s();
         if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 2e-4)));
         continue;
       }
       break;
     }
+    // 2. imports of the admitted records, beside the iterations in flight
     if (nadm > 0) {
-      if (hipMemcpyAsync(d_adm, h_adm, nadm * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)
-        return STRATEGO_E_HIP;
-      const size_t first_new = active.size() - admitted.size();
-      for (size_t k = 0; k < admitted.size(); ++k) {
-        const Active& a = active[first_new + k];
-        const stratego_request& q = reqs[a.req];
-        hipLaunchKernelGGL(k_import, dim3(grid_for(q.num_games, 4)), dim3(256), 4 * kSlabImage, c->stream,
-                           c->states, d_adm + admitted[k], q.num_games, N, in + (size_t)q.first * kRecordBytes,
+      if (hipMemcpyAsync(d_adm[b], h_adm[b], nadm * sizeof(int32_t), hipMemcpyHostToDevice, c->copy_stream) !=
+          hipSuccess) { rc = STRATEGO_E_HIP; break; }
+      for (int r : admitted) {
+        const stratego_request& q = reqs[r];
+        hipLaunchKernelGGL(k_import, dim3(grid_for(q.num_games, 4)), dim3(256), 4 * kSlabImage, c->copy_stream,
+                           c->states, d_adm[b] + adm_off[r], q.num_games, N, in + (size_t)q.first * kRecordBytes,
                            c->err);
       }
+      if (hipEventRecord(ev_import[b], c->copy_stream) != hipSuccess ||
+          hipStreamWaitEvent(c->stream, ev_import[b], 0) != hipSuccess) { rc = STRATEGO_E_HIP; break; }
     }
-    // 2. one fused ply for every active game: step requests with observations,
-    //    rollout requests without
+    // 3. one fused ply for every active game: step requests with
+    //    observations, rollout requests without
     int nstep = 0, nroll = 0;
-    std::vector<int> run_off(active.size());
-    for (size_t k = 0; k < active.size(); ++k) {
-      const Active& a = active[k];
-      const stratego_request& q = reqs[a.req];
+    for (int r : active) {
+      const stratego_request& q = reqs[r];
+      const int32_t* sl = slot_store.data() + seg[r];
       if (q.kind == STRATEGO_REQ_STEP) {
-        run_off[k] = nstep;
+        run_off[r] = nstep;
         for (int j = 0; j < q.num_games; ++j) {
-          h_step[nstep + j] = a.slots[j];
-          h_oidx[nstep + j] = obs_by_slot ? a.slots[j] : q.first + j;
+          h_step[b][nstep + j] = sl[j];
+          h_oidx[b][nstep + j] = obs_by_slot ? sl[j] : q.first + j;
         }
         nstep += q.num_games;
       } else {
-        run_off[k] = nroll;
-        for (int j = 0; j < q.num_games; ++j) h_roll[nroll + j] = a.slots[j];
+        run_off[r] = nroll;
+        for (int j = 0; j < q.num_games; ++j) h_roll[b][nroll + j] = sl[j];
         nroll += q.num_games;
       }
     }
-    if (nstep > 0 &&
-        (hipMemcpyAsync(d_step, h_step, nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-         hipMemcpyAsync(d_oidx, h_oidx, nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess))
-      return STRATEGO_E_HIP;
-    if (nroll > 0 &&
-        hipMemcpyAsync(d_roll, h_roll, nroll * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)
-      return STRATEGO_E_HIP;
+    if ((nstep > 0 &&
+         (hipMemcpyAsync(d_step[b], h_step[b], nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+          hipMemcpyAsync(d_oidx[b], h_oidx[b], nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)) ||
+        (nroll > 0 &&
+         hipMemcpyAsync(d_roll[b], h_roll[b], nroll * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)) {
+      rc = STRATEGO_E_HIP;
+      break;
+    }
+    if (hipEventRecord(ev_start[b], c->stream) != hipSuccess) { rc = STRATEGO_E_HIP; break; }
+    if (iterations == 0 && hipEventRecord(ev_first, c->stream) != hipSuccess) { rc = STRATEGO_E_HIP; break; }
     if (nstep > 0) {
       PlyArgs a = base_args(c);
-      a.slots = d_step;
+      a.slots = d_step[b];
       a.n = nstep;
-      a.out_index = d_oidx;
+      a.out_index = d_oidx[b];
       a.obs = obs_out;
-      int rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
-      if (rc != STRATEGO_OK) return rc;
+      rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
+      if (rc != STRATEGO_OK) break;
     }
     if (nroll > 0) {
       PlyArgs a = base_args(c);
-      a.slots = d_roll;
+      a.slots = d_roll[b];
       a.n = nroll;
-      int rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
-      if (rc != STRATEGO_OK) return rc;
+      rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
+      if (rc != STRATEGO_OK) break;
     }
     game_steps += nstep + nroll;
-    // 3. retire requests whose plies are done: copy their records out
-    std::vector<size_t> finished;
-    for (size_t k = 0; k < active.size(); ++k) {
-      Active& a = active[k];
-      if (--a.remaining > 0) continue;
-      const stratego_request& q = reqs[a.req];
-      const int32_t* list = (q.kind == STRATEGO_REQ_STEP ? d_step : d_roll) + run_off[k];
+    // 4. requests whose last ply this is: copy their records out; their
+    //    slots are free once this iteration has completed
+    size_t keep = 0;
+    for (size_t ai = 0; ai < active.size(); ++ai) {
+      const int r = active[ai];
+      if (--remaining[r] > 0) { active[keep++] = r; continue; }
+      const stratego_request& q = reqs[r];
+      const int32_t* list = (q.kind == STRATEGO_REQ_STEP ? d_step[b] : d_roll[b]) + run_off[r];
       hipLaunchKernelGGL(k_gather, dim3(grid_for(q.num_games, 4)), dim3(256), 0, c->stream, c->states, list,
                          q.num_games, out + (size_t)q.first * kRecordBytes);
-      finished.push_back(k);
-    }
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return STRATEGO_E_HIP;
-    ++iterations;
-    t = now_s();
-    for (size_t f = finished.size(); f-- > 0;) {
-      Active& a = active[finished[f]];
-      const stratego_request& q = reqs[a.req];
-      results[a.req].done_s = t;
-      for (int32_t sl : a.slots) free_slots.push_back(sl);
+      finishing[b].push_back(r);
+      for (int j = 0; j < q.num_games; ++j) pend_free[b].push_back(slot_store[(size_t)seg[r] + j]);
       reserved -= bytes_of(q);
       active_games -= q.num_games;
-      ++completed;
-      active.erase(active.begin() + (long)finished[f]);
     }
+    active.resize(keep);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(ev_end[b], c->stream) != hipSuccess) {
+      rc = STRATEGO_E_HIP;
+      break;
+    }
+    ++inflight;
+    ++iterations;
+    ++k;
   }
+  while (inflight > 0 && rc == STRATEGO_OK) retire();
+  if (rc == STRATEGO_OK && iterations > 0) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev_ref, ev_first);
+    first_ms = ms;
+  }
+  if (rc != STRATEGO_OK) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->copy_stream);
+  destroy_events();
+  if (rc != STRATEGO_OK) return rc;
   c->steps += game_steps;
   if (stats) {
     stats->wall_s = now_s();
@@ -1537,6 +1617,8 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
     stats->peak_active_games = peak_active;
     stats->peak_reserved_bytes = peak_reserved;
     stats->budget_bytes = budget;
+    stats->gpu_busy_s = busy_ms / 1e3;
+    stats->gpu_span_s = iterations > 0 ? (last_end_ms - first_ms) / 1e3 : 0.0;
   }
   return STRATEGO_OK;
 }
@@ -1854,6 +1936,7 @@ int stratego_destroy(stratego_ctx* c) {
   for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
   c->graphs.clear();
   (void)hipStreamDestroy(c->capture_stream);
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
   if (c->tickets) (void)hipFree(c->tickets);
   if (c->srv_dev) (void)hipFree(c->srv_dev);
   if (c->srv_host) (void)hipHostFree(c->srv_host);

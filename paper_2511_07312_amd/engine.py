@@ -91,7 +91,8 @@ class RequestResult(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [("wall_s", ctypes.c_double), ("game_steps", ctypes.c_int64),
                 ("iterations", ctypes.c_int32), ("peak_active_games", ctypes.c_int32),
-                ("peak_reserved_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64)]
+                ("peak_reserved_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
+                ("gpu_busy_s", ctypes.c_double), ("gpu_span_s", ctypes.c_double)]
 
 
 class StrategoError(RuntimeError):

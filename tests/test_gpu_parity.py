@@ -464,6 +464,7 @@ def test_serving_results_same_alone_and_in_the_mix():
     assert eng.error() == (0, -1)
     assert stats["game_steps"] == sum(b * p for _, p, b, _, _ in reqs)
     assert stats["peak_reserved_bytes"] <= budget
+    assert 0 < stats["gpu_busy_s"] <= stats["gpu_span_s"] * 1.001 and stats["gpu_span_s"] <= stats["wall_s"]
     for (a, d), q in zip(res, reqs):
         assert q[4] <= a + 1e-3 and a <= d
     out_mix_h, obs_mix_h = cpu(out_mix), cpu(obs_mix)
