@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # mask 1256 written, num_legal 2, action 2, done/outcome/reason/ep_len 5,
 # state record 1536 read + 1536 written
 BYTES_PER_GAME_STEP = 97600 + 1256 + 2 + 2 + 5 + 2 * 1536
+EXTRA_LEGS = ("rollout_buffer", "rules", "policies", "acting", "search", "steady")
 
 
 def percentile(xs, q):
@@ -499,6 +500,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated subset of the extra legs to run: rollout_buffer, rules, policies, "
+                         "acting, search, steady (default: all unless --no-extras)")
     ap.add_argument("--no-extras", "--no-history", dest="no_history", action="store_true",
                     help="skip the rollout-buffer, rules, policy, acting-player and search legs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -615,17 +619,23 @@ def main():
     torch.cuda.empty_cache()
     serving = None if args.no_serving else serving_bench(E, torch)
     torch.cuda.empty_cache()
-    rollout_buffer = None if args.no_history else rollout_buffer_bench(E, torch, n)
+    legs = set(EXTRA_LEGS) if args.legs is None and not args.no_history else set()
+    if args.legs:
+        legs = set(x.strip() for x in args.legs.split(",") if x.strip())
+        unknown = legs - set(EXTRA_LEGS)
+        if unknown:
+            raise SystemExit(f"unknown legs {sorted(unknown)}; known: {', '.join(EXTRA_LEGS)}")
+    rollout_buffer = rollout_buffer_bench(E, torch, n) if "rollout_buffer" in legs else None
     torch.cuda.empty_cache()
-    two_square = None if args.no_history else two_square_bench(E, torch, n)
+    two_square = two_square_bench(E, torch, n) if "rules" in legs else None
     torch.cuda.empty_cache()
-    policies = None if args.no_history else policy_bench(E, torch, n)
+    policies = policy_bench(E, torch, n) if "policies" in legs else None
     torch.cuda.empty_cache()
-    acting = None if args.no_history else acting_player_bench(E, torch, n)
+    acting = acting_player_bench(E, torch, n) if "acting" in legs else None
     torch.cuda.empty_cache()
-    search = None if args.no_history else search_bench(E, torch)
+    search = search_bench(E, torch) if "search" in legs else None
     torch.cuda.empty_cache()
-    steady = None if args.no_history else steady_state_bench(E, torch, G, S, n)
+    steady = steady_state_bench(E, torch, G, S, n) if "steady" in legs else None
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
