@@ -104,7 +104,7 @@ def cpu_baseline(seconds=12.0):
                        f"{el:.1f} s wall")
 
 
-def serving_bench(E, torch, n_requests=240, seed=4):
+def serving_bench(E, torch, n_requests=2000, seed=4):
     """Continuous-batching serving: Poisson arrivals, half step requests (one
     ply with both observations) and half k-ply rollouts (k uniform in 1..128),
     batch sizes floor(exp(U(0, ln 16384))), start states drawn from games of
