@@ -98,6 +98,50 @@ __host__ __device__ __forceinline__ constexpr int ply_wave_lds_bytes(int enc, in
 }
 static_assert(kNoObsSlabBytes % 16 == 0, "record buffers stay 16-byte aligned");
 
+// An entry of an index list at a wave-uniform position, read through the
+// scalar unit (the lists are not written during a launch), so that no wait on
+// the vector-memory counter, which also holds the stores in flight, is needed
+// for it.
+__device__ __forceinline__ int32_t uniform_load(const int32_t* list, int idx) {
+  idx = __builtin_amdgcn_readfirstlane(idx);
+  return ((const __attribute__((address_space(4))) int32_t*)list)[idx];
+}
+
+// A record as two 768-byte halves, 12 bytes per lane: every lane takes part
+// in both accesses, so no branch can skip one.  (A skipped access would leave
+// the compiler unsure which loads are still in flight, and it would then wait
+// for all of them, stores included.)
+struct __attribute__((aligned(4))) Rec12 {
+  uint32_t x, y, z;
+};
+struct RecRegs {
+  Rec12 lo, hi;
+};
+__device__ __forceinline__ RecRegs rec_load(const uint8_t* g) {
+  const int lane = lane_id();
+  const Rec12* src = reinterpret_cast<const Rec12*>(g);
+  return RecRegs{src[lane], src[64 + lane]};
+}
+__device__ __forceinline__ void rec_store(uint8_t* g, const RecRegs& r) {
+  const int lane = lane_id();
+  Rec12* dst = reinterpret_cast<Rec12*>(g);
+  dst[lane] = r.lo;
+  dst[64 + lane] = r.hi;
+}
+
+// A game's mask words and legal-move count.
+__device__ __forceinline__ void store_mask_outputs(const PlyArgs& a, int oi, const uint64_t w[3], int n,
+                                                   bool with_mask) {
+  const int lane = lane_id();
+  if (with_mask && a.mask) {
+    uint64_t* m = a.mask + (size_t)oi * kMaskWords;
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+      if (lane + 64 * g < kMaskWords) m[lane + 64 * g] = w[g];
+  }
+  if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
+}
+
 // FAST: the fused ply's register-board path (drawn actions, neither
 // competitive-play rule on); otherwise the general path.  NOMASK: no mask
 // output (a.mask is NULL), so the ply samples from move counts alone.
@@ -134,19 +178,21 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   int gi = 0;
   int i = tile < ntiles ? tile * G + gi : a.n;
   bool have = i < a.n;
-  int slot = have ? (a.slots ? a.slots[i] : i) : 0;
+  int slot = have ? (a.slots ? uniform_load(a.slots, i) : i) : 0;
   bool slot_ok = have && slot >= 0 && slot < a.total;
   if (slot_ok) load_record(slab, a.states + (size_t)slot * kRecordBytes);
   int cur = 0;   // offset of the current record buffer: 0 or spare
   // Plies without observations write a game's results and record back only
-  // after the next game's record has been requested: one counter tracks
-  // loads and stores in issue order, so waiting for that load then does not
-  // wait for these stores too.  The pending record is in the other buffer.
+  // once the next game's record has arrived: one counter tracks loads and
+  // stores in issue order, so a wait for a load also waits for every store
+  // issued before it.  The pending record sits in the other buffer until the
+  // next record is parked there; it is read into registers first and stored
+  // after the park, so that no wait follows these stores within the game.
   constexpr bool kDefer = ENC == kEncNone && (MODE & kDoStep) != 0;
   uint8_t* pend_g = nullptr;    // where the pending record goes (NULL: none)
   size_t pend_row = 0;
   StepOut pend_o{0, 0, 0, 0, false};
-  auto flush = [&]() {
+  auto flush = [&](const RecRegs& r) {
     if (!kDefer || pend_g == nullptr) return;
     if (lane == 0) {
       if (a.done) a.done[pend_row] = (int8_t)pend_o.done;
@@ -154,7 +200,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       if (a.reason) a.reason[pend_row] = (uint8_t)pend_o.reason;
       if (a.ep_len) a.ep_len[pend_row] = (int16_t)pend_o.ep_len;
     }
-    store_record(pend_g, slab + (spare - cur));
+    rec_store(pend_g, r);
     pend_g = nullptr;
   };
   while (have) {
@@ -177,32 +223,47 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       inext = ntile < ntiles ? ntile * G + ngi : a.n;
       next_have = inext < a.n;
       if (next_have) {
-        next_slot = a.slots ? a.slots[inext] : inext;
+        next_slot = a.slots ? uniform_load(a.slots, inext) : inext;
         next_ok = next_slot >= 0 && next_slot < a.total;
       }
     };
     if (!need_grab) resolve_next();
     uint4 p0 = make_uint4(0, 0, 0, 0), p1 = make_uint4(0, 0, 0, 0);
+    RecRegs pn{};
     bool fetched = false;
     auto fetch_next = [&]() {
       resolve_next();
       if (next_ok && !fetched) {
-        const uint4* src = reinterpret_cast<const uint4*>(a.states + (size_t)next_slot * kRecordBytes);
-        p0 = src[lane];
-        if (lane < 32) p1 = src[64 + lane];
+        const uint8_t* g = a.states + (size_t)next_slot * kRecordBytes;
+        if (kDefer) {
+          pn = rec_load(g);
+        } else {
+          const uint4* src = reinterpret_cast<const uint4*>(g);
+          p0 = src[lane];
+          if (lane < 32) p1 = src[64 + lane];
+        }
       }
       fetched = true;
-      flush();   // the previous game's write-back, behind this load
     };
     bool parked = false;
     auto park_next = [&]() {
       fetch_next();
-      if (next_ok && !parked) {
-        uint4* dst = reinterpret_cast<uint4*>(slab + (spare - cur));
+      if (parked) return;
+      parked = true;
+      uint8_t* spare_buf = slab + (spare - cur);
+      if (kDefer) {
+        // the previous game's record leaves the spare buffer before the next
+        // one is parked there (zeros when there is no next game), and is
+        // stored only after that park
+        RecRegs r{};
+        if (pend_g != nullptr) r = rec_load(spare_buf);
+        rec_store(spare_buf, pn);
+        flush(r);
+      } else if (next_ok) {
+        uint4* dst = reinterpret_cast<uint4*>(spare_buf);
         dst[lane] = p0;
         if (lane < 32) dst[64 + lane] = p1;
       }
-      parked = true;
     };
     if (!slot_ok) {
       if (lane == 0) atomicMin(&a.err[1], i);
@@ -210,13 +271,13 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     } else {
       uint8_t* R = slab + cur;
       uint8_t* gstate = a.states + (size_t)slot * kRecordBytes;
-      const int oi = a.out_index ? a.out_index[i] : i;
+      const int oi = a.out_index ? uniform_load(a.out_index, i) : i;
       int action = -1;
       SquareRegs rg;
+      uint64_t w[3] = {0ull, 0ull, 0ull};
+      int n = 0;
       if (MODE & kDoMask) {
-        uint64_t w[3];
         uint64_t d[4];
-        int n;
         uint32_t pk[2];
         if (FAST) {
           // with a mask to write, the destination sets; else counts suffice
@@ -235,13 +296,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
           n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
         }
         fetch_next();
-        if (!NOMASK && a.mask) {
-          uint64_t* m = a.mask + (size_t)oi * kMaskWords;
-#pragma unroll
-          for (int g = 0; g < 3; ++g)
-            if (lane + 64 * g < kMaskWords) m[lane + 64 * g] = w[g];
-        }
-        if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
+        if (!kDefer) store_mask_outputs(a, oi, w, n, !NOMASK);
         if (FAST && (MODE & kDoSample)) {
           // wave-uniform copies, so that the generator and the selection run
           // on the scalar unit
@@ -254,7 +309,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
           else
             action = magnet ? (n == 0 ? -1 : magnet_counts(pk, a.rules.seed, gid, ply, ep))
                             : sample_counts(pk, n, a.rules.seed, gid, ply, ep);
-          if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
+          if (!kDefer && a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
         } else if (MODE & kDoSample) {
           if (a.rules.sampler == kSamplerMagnet) {
             const uint64_t* ts = reinterpret_cast<const uint64_t*>(slab + kSlabImage);
@@ -267,12 +322,16 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
             action = sample_from_words(w, n, a.rules.seed, hdr_u32(R, kOffGameId),
                                        hdr_u32(R, kOffPly), hdr_u32(R, kOffEpisode));
           }
-          if (a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
+          if (!kDefer && a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
         }
         wave_sync();
         if (byte_image) clear_lds(slab + kSlabImage, kDestSetBytes);
       }
       park_next();
+      if (kDefer && (MODE & kDoMask)) {   // this game's mask outputs, behind the park
+        store_mask_outputs(a, oi, w, n, !NOMASK);
+        if ((MODE & kDoSample) && a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
+      }
       if (MODE & kStepFromInput) action = a.actions_in[i];
       if (encode) {
         compute_probq(R, slab);
@@ -317,7 +376,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     have = next_have;
     cur = spare - cur;
   }
-  flush();
+  if (kDefer && pend_g != nullptr) flush(rec_load(slab + (spare - cur)));   // the last game's write-back
   if (a.ts) {
     __syncthreads();
     if (threadIdx.x == 0) atomicMax(&a.ts[1], (unsigned long long)wall_clock64());
