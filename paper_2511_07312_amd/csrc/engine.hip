@@ -182,24 +182,17 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   bool slot_ok = have && slot >= 0 && slot < a.total;
   if (slot_ok) load_record(slab, a.states + (size_t)slot * kRecordBytes);
   int cur = 0;   // offset of the current record buffer: 0 or spare
-  // Plies without observations write a game's results and record back only
-  // once the next game's record has arrived: one counter tracks loads and
-  // stores in issue order, so a wait for a load also waits for every store
-  // issued before it.  The pending record sits in the other buffer until the
-  // next record is parked there; it is read into registers first and stored
-  // after the park, so that no wait follows these stores within the game.
+  // Plies without observations write a game's record back only once the
+  // next game's record has arrived: one counter tracks loads and stores in
+  // issue order, so a wait for a load also waits for every store issued
+  // before it.  The pending record sits in the other buffer until the next
+  // record is parked there; it is read into registers first and stored after
+  // the park, so that no wait follows these stores within the game.  (The
+  // few bytes of per-game results are stored right after the step.)
   constexpr bool kDefer = ENC == kEncNone && (MODE & kDoStep) != 0;
   uint8_t* pend_g = nullptr;    // where the pending record goes (NULL: none)
-  size_t pend_row = 0;
-  StepOut pend_o{0, 0, 0, 0, false};
   auto flush = [&](const RecRegs& r) {
     if (!kDefer || pend_g == nullptr) return;
-    if (lane == 0) {
-      if (a.done) a.done[pend_row] = (int8_t)pend_o.done;
-      if (a.outcome) a.outcome[pend_row] = (int8_t)pend_o.outcome;
-      if (a.reason) a.reason[pend_row] = (uint8_t)pend_o.reason;
-      if (a.ep_len) a.ep_len[pend_row] = (int16_t)pend_o.ep_len;
-    }
     rec_store(pend_g, r);
     pend_g = nullptr;
   };
@@ -347,20 +340,16 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
                                                                     a.rules, action);
         const size_t row = (size_t)a.out_base + oi;
         if (lane == 0) {
-          if (!kDefer) {
-            if (a.done) a.done[row] = (int8_t)o.done;
-            if (a.outcome) a.outcome[row] = (int8_t)o.outcome;
-            if (a.reason) a.reason[row] = (uint8_t)o.reason;
-            if (a.ep_len) a.ep_len[row] = (int16_t)o.ep_len;
-          }
+          if (a.done) a.done[row] = (int8_t)o.done;
+          if (a.outcome) a.outcome[row] = (int8_t)o.outcome;
+          if (a.reason) a.reason[row] = (uint8_t)o.reason;
+          if (a.ep_len) a.ep_len[row] = (int16_t)o.ep_len;
           if (o.illegal) atomicMin(&a.err[0], slot);
           if (a.hist) a.hist_steps[hist_row + slot] = pack_step(action, o);
         }
         wave_sync();
         if (kDefer) {
           pend_g = gstate;
-          pend_row = row;
-          pend_o = o;
         } else {
           store_record(gstate, R);
         }
