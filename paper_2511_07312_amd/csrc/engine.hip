@@ -241,10 +241,10 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     bool parked = false;
     auto park_next = [&]() {
       fetch_next();
-      if (parked) return;
-      parked = true;
-      uint8_t* spare_buf = slab + (spare - cur);
-      if (kDefer) {
+      if constexpr (kDefer) {
+        if (parked) return;
+        parked = true;
+        uint8_t* spare_buf = slab + (spare - cur);
         // the previous game's record leaves the spare buffer before the next
         // one is parked there (zeros when there is no next game), and is
         // stored only after that park
@@ -252,10 +252,13 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
         if (pend_g != nullptr) r = rec_load(spare_buf);
         rec_store(spare_buf, pn);
         flush(r);
-      } else if (next_ok) {
-        uint4* dst = reinterpret_cast<uint4*>(spare_buf);
-        dst[lane] = p0;
-        if (lane < 32) dst[64 + lane] = p1;
+      } else {
+        if (next_ok && !parked) {
+          uint4* dst = reinterpret_cast<uint4*>(slab + (spare - cur));
+          dst[lane] = p0;
+          if (lane < 32) dst[64 + lane] = p1;
+        }
+        parked = true;
       }
     };
     if (!slot_ok) {
@@ -267,8 +270,8 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       const int oi = a.out_index ? uniform_load(a.out_index, i) : i;
       int action = -1;
       SquareRegs rg;
-      uint64_t w[3] = {0ull, 0ull, 0ull};
-      int n = 0;
+      uint64_t w[3];
+      int n;
       if (MODE & kDoMask) {
         uint64_t d[4];
         uint32_t pk[2];
@@ -289,7 +292,15 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
           n = legal_mask_words(R, reinterpret_cast<uint64_t*>(slab + kSlabImage), w, a.rules, slab + kSlabProbQ);
         }
         fetch_next();
-        if (!kDefer) store_mask_outputs(a, oi, w, n, !NOMASK);
+        if (!kDefer) {
+          if (!NOMASK && a.mask) {
+            uint64_t* m = a.mask + (size_t)oi * kMaskWords;
+#pragma unroll
+            for (int g = 0; g < 3; ++g)
+              if (lane + 64 * g < kMaskWords) m[lane + 64 * g] = w[g];
+          }
+          if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
+        }
         if (FAST && (MODE & kDoSample)) {
           // wave-uniform copies, so that the generator and the selection run
           // on the scalar unit
