@@ -104,12 +104,14 @@ def cpu_baseline(seconds=12.0):
                        f"{el:.1f} s wall")
 
 
-def serving_bench(E, torch, n_requests=2000, seed=4):
+def serving_bench(E, torch, n_requests=2000, seed=4, backfill_wait_s=0.005):
     """Continuous-batching serving: Poisson arrivals, half step requests (one
     ply with both observations) and half k-ply rollouts (k uniform in 1..128),
     batch sizes floor(exp(U(0, ln 16384))), start states drawn from games of
-    random play without auto-reset.  Measures the saturated rate, then p50/p99
-    latency and throughput at 0.3, 0.6 and 0.9 of it."""
+    random play without auto-reset.  Admission backfills: a request that does
+    not fit lets later ones go ahead for up to backfill_wait_s (< 0: strict
+    arrival order).  Measures the saturated rate, then p50/p99 latency and
+    throughput at 0.3, 0.6 and 0.9 of it."""
     import math
     import numpy as np
     rng = np.random.default_rng(seed)
@@ -139,7 +141,8 @@ def serving_bench(E, torch, n_requests=2000, seed=4):
         reqs = [(int(kinds[r]), int(plies[r]), int(sizes[r]), int(firsts[r]), float(arr[r]))
                 for r in range(n_requests)]
         res, st = E.stratego_serve(eng.ctx, reqs, inp, out, obs_pool, obs_by_slot=True,
-                                   mem_budget_bytes=0, realtime=rate is not None)
+                                   mem_budget_bytes=0, realtime=rate is not None,
+                                   backfill_wait_s=backfill_wait_s)
         lat = {0: [], 1: []}
         for r, (a, d) in enumerate(res):
             lat[int(kinds[r])].append((d - arr[r]) * 1e3)
@@ -163,7 +166,7 @@ def serving_bench(E, torch, n_requests=2000, seed=4):
     assert eng.error() == (0, -1)
     eng.close()
     return dict(unit="game steps/s", saturated=sat, saturated_gpu_idle_fraction=sat_idle,
-                requests=n_requests, games=total,
+                requests=n_requests, games=total, backfill_wait_s=backfill_wait_s,
                 pool_slots=slots, rates=out_rates)
 
 
@@ -500,6 +503,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-backfill-ms", type=float, default=5.0,
+                    help="how long a serving request that does not fit lets later ones go ahead of it "
+                         "(negative: strict arrival order)")
     ap.add_argument("--legs", default=None,
                     help="comma-separated subset of the extra legs to run: rollout_buffer, rules, policies, "
                          "acting, search, steady (default: all unless --no-extras)")
@@ -617,7 +623,7 @@ def main():
     eng.close()
     del obs, eng
     torch.cuda.empty_cache()
-    serving = None if args.no_serving else serving_bench(E, torch)
+    serving = None if args.no_serving else serving_bench(E, torch, backfill_wait_s=args.serving_backfill_ms / 1e3)
     torch.cuda.empty_cache()
     legs = set(EXTRA_LEGS) if args.legs is None and not args.no_history else set()
     if args.legs:

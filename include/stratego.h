@@ -240,12 +240,17 @@ int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int3
  * acting_obs_only) are written to obs_out_dev
  * at rows first + j, or at the game's pool slot when obs_by_slot = 1) and
  * STRATEGO_REQ_ROLLOUT (no observations).  The context's N slots are the
- * device-resident pool.  Requests are admitted first come first served, as
- * soon as they have arrived (realtime = 1: at arrival_s seconds after the call
- * starts; realtime = 0: all at once) and both enough free slots and enough of
+ * device-resident pool.  Requests are admitted in arrival order, once they
+ * have arrived (realtime = 1: at arrival_s seconds after the call starts;
+ * realtime = 0: all at once) and while both enough free slots and enough of
  * the memory budget remain (a game reserves 1536 bytes, plus its observation
  * bytes, 97600 or 48800, for step requests); mem_budget_bytes <= 0 uses the
- * device's free memory at the start of the call.  Every iteration runs one
+ * device's free memory at the start of the call.  A request that does not
+ * fit lets later arrived requests that fit go ahead of it (backfilling) until
+ * it has waited backfill_wait_s seconds since its arrival (since the call's
+ * start with realtime = 0); from then on nothing is admitted before it, so it
+ * enters as soon as enough slots have freed.  backfill_wait_s < 0 admits in
+ * strict arrival order.  Every iteration runs one
  * fused ply over all admitted games, so requests that arrive while others run
  * join them on the device; a request leaves after its last ply, when its
  * final records are copied to rows [first, first + num_games) of
@@ -287,7 +292,8 @@ typedef struct {
 int stratego_serve(stratego_ctx* ctx, const stratego_request* reqs, int32_t nreq,
                    const void* in_states_dev, void* out_states_dev, uint8_t* obs_out_dev,
                    int32_t obs_by_slot, int64_t mem_budget_bytes, int32_t realtime,
-                   stratego_request_result* results, stratego_serve_stats* stats);
+                   double backfill_wait_s, stratego_request_result* results,
+                   stratego_serve_stats* stats);
 
 /* Time the fused engine for every (games_per_wg, lds_layout) pair that fits
  * the device, plies plies each, restoring the game states afterwards, and

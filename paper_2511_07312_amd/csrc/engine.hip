@@ -1426,8 +1426,10 @@ int stratego_reset_resampled(stratego_ctx* c, const void* src, int32_t nsrc, int
 
 int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, const void* in_states,
                    void* out_states, uint8_t* obs_out, int32_t obs_by_slot, int64_t mem_budget,
-                   int32_t realtime, stratego_request_result* results, stratego_serve_stats* stats) {
-  if (!c || nreq < 0 || (nreq > 0 && (!reqs || !in_states || !out_states || !results)))
+                   int32_t realtime, double backfill_wait_s, stratego_request_result* results,
+                   stratego_serve_stats* stats) {
+  if (!c || nreq < 0 || (nreq > 0 && (!reqs || !in_states || !out_states || !results)) ||
+      !(backfill_wait_s == backfill_wait_s))
     return STRATEGO_E_INVAL;
   if (c->hist) return STRATEGO_E_INVAL;   // the rollout buffer indexes whole-batch plies
   const int N = c->cfg.num_games;
@@ -1469,6 +1471,7 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
                    [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
   std::vector<int32_t> slot_store((size_t)total_games);   // slots of request r from seg[r]
   std::vector<int64_t> seg(nreq, 0);
+  std::vector<char> is_admitted(nreq, 0);
   std::vector<int32_t> remaining(nreq, 0), adm_off(nreq, 0), run_off(nreq, 0);
   std::vector<int> active, admitted, finishing[2];
   active.reserve(nreq);
@@ -1536,16 +1539,25 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
   while (rc == STRATEGO_OK && completed < nreq) {
     const int b = (int)(k & 1);
     if (inflight == 2) { retire(); if (rc != STRATEGO_OK) break; }
-    // 1. admit arrived requests, first come first served, while free slots
-    //    and the memory budget allow
+    // 1. admit arrived requests in arrival order while free slots and the
+    //    memory budget allow.  One that does not fit lets later ones that do
+    //    go ahead (backfilling) until it has waited backfill_wait_s; from
+    //    then on it holds its place, so that it is admitted as soon as enough
+    //    slots have freed.  (backfill_wait_s < 0: strict arrival order.)
     const double t = now_s();
     int nadm = 0;
     admitted.clear();
-    while (next < nreq) {
-      const int r = order[next];
+    for (int j = next; j < nreq; ++j) {
+      const int r = order[j];
+      if (is_admitted[r]) continue;
       const stratego_request& q = reqs[r];
       if (realtime && q.arrival_s > t) break;
-      if ((int)free_now.size() < q.num_games || reserved + bytes_of(q) > budget) break;
+      if ((int)free_now.size() < q.num_games || reserved + bytes_of(q) > budget) {
+        const double waited = t - (realtime ? q.arrival_s : 0.0);
+        if (backfill_wait_s < 0.0 || waited > backfill_wait_s) break;
+        continue;
+      }
+      is_admitted[r] = 1;
       seg[r] = seg_next;
       seg_next += q.num_games;
       adm_off[r] = nadm;
@@ -1562,8 +1574,8 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
       results[r].admit_s = t;
       active.push_back(r);
       admitted.push_back(r);
-      ++next;
     }
+    while (next < nreq && is_admitted[order[next]]) ++next;   // first request not yet admitted
     peak_reserved = std::max(peak_reserved, reserved);
     peak_active = std::max(peak_active, active_games);
     if (active.empty()) {

@@ -131,7 +131,8 @@ def load_library(path=LIB_PATH):
     L.stratego_current_step.argtypes = [P, ctypes.POINTER(I64)]
     L.stratego_destroy.argtypes = [P]
     L.stratego_serve.argtypes = [P, ctypes.POINTER(Request), I32, P, P, P, I32, I64, I32,
-                                 ctypes.POINTER(RequestResult), ctypes.POINTER(ServeStats)]
+                                 ctypes.c_double, ctypes.POINTER(RequestResult),
+                                 ctypes.POINTER(ServeStats)]
     L.stratego_history_window.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.stratego_history_legal_mask.argtypes = [P, I64, P, I32, P, P]
     L.stratego_history_encode_obs.argtypes = [P, I64, P, I32, P]
@@ -412,8 +413,10 @@ def stratego_autotune(ctx, obs, mask, plies=3, max_entries=64):
 
 
 def stratego_serve(ctx, requests, in_states, out_states, obs_out=None, obs_by_slot=False,
-                   mem_budget_bytes=0, realtime=True):
+                   mem_budget_bytes=0, realtime=True, backfill_wait_s=-1.0):
     """requests: sequence of (kind, plies, num_games, first, arrival_s).
+    backfill_wait_s < 0: strict arrival order; otherwise how long a request
+    that does not fit lets later ones go ahead of it.
     Returns (list of (admit_s, done_s), stats dict)."""
     nreq = len(requests)
     reqs = (Request * max(nreq, 1))()
@@ -428,7 +431,8 @@ def stratego_serve(ctx, requests, in_states, out_states, obs_out=None, obs_by_sl
         ctx, reqs, nreq, _ptr(in_states, torch.uint8, total * RECORD_BYTES, "in_states"),
         _ptr(out_states, torch.uint8, total * RECORD_BYTES, "out_states"),
         _ptr(obs_out, torch.uint8, obs_rows, "obs_out"), int(bool(obs_by_slot)),
-        int(mem_budget_bytes), int(bool(realtime)), res, ctypes.byref(st)), "stratego_serve")
+        int(mem_budget_bytes), int(bool(realtime)), float(backfill_wait_s), res, ctypes.byref(st)),
+        "stratego_serve")
     stats = {k: getattr(st, k) for k, _ in ServeStats._fields_}
     return [(res[r].admit_s, res[r].done_s) for r in range(nreq)], stats
 

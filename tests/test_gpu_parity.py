@@ -485,6 +485,33 @@ def test_serving_results_same_alone_and_in_the_mix():
     eng.close()
 
 
+def test_serving_backfill_admits_smaller_requests_first():
+    """Admission order with and without backfilling, on a 100-slot pool: a
+    50-game request that cannot fit beside a running 90-game one holds back a
+    later 5-game request in strict arrival order, and lets it go ahead with
+    backfilling.  Every request's final states are the same either way."""
+    recs = serving_inputs(145)
+    inp = torch.from_numpy(recs).cuda()
+    reqs = [(E.REQ_ROLLOUT, 20, 90, 0, 0.0),     # fills 90 of the 100 slots for 20 plies
+            (E.REQ_ROLLOUT, 1, 50, 90, 0.0),     # does not fit until it leaves
+            (E.REQ_STEP, 1, 5, 140, 0.0)]        # fits beside it
+    outs, admits = {}, {}
+    for name, wait in (("strict", -1.0), ("backfill", 10.0)):
+        eng = E.Engine(100, 3, k_battleless=100, max_moves=1000, auto_reset=False)
+        out = torch.zeros_like(inp)
+        obs = torch.zeros((145, 2, 488, 10, 10), dtype=torch.uint8, device="cuda")
+        res, stats = E.stratego_serve(eng.ctx, reqs, inp, out, obs, realtime=False, backfill_wait_s=wait)
+        assert eng.error() == (0, -1)
+        assert stats["peak_active_games"] <= 100
+        admits[name] = [a for a, _ in res]
+        outs[name] = cpu(out)
+        eng.close()
+    s_adm, b_adm = admits["strict"], admits["backfill"]
+    assert s_adm[0] <= s_adm[1] <= s_adm[2], s_adm       # arrival order
+    assert b_adm[2] < b_adm[1], b_adm                    # the 5 games went ahead
+    assert_same("final states, strict vs backfill", outs["strict"], outs["backfill"])
+
+
 # ---------------------------------------------------------------- full size
 def test_65536_games_whole_population_graph_plies():
     """The benchmark's configuration (65,536 games, auto-reset, autotuned
