@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # mask 1256 written, num_legal 2, action 2, done/outcome/reason/ep_len 5,
 # state record 1536 read + 1536 written
 BYTES_PER_GAME_STEP = 97600 + 1256 + 2 + 2 + 5 + 2 * 1536
-EXTRA_LEGS = ("rollout_buffer", "rules", "policies", "acting", "search", "steady")
+EXTRA_LEGS = ("rollout_buffer", "rules", "policies", "acting", "search", "steady", "small")
 
 
 def percentile(xs, q):
@@ -489,6 +489,73 @@ def latency_bench(E, torch, eng, obs, samples=200):
     return out
 
 
+def small_batch_bench(E, torch, sizes=(256, 4096), plies=192):
+    """Small batches, where launches rather than bytes set the time: per-ply
+    latency of the plain engine (four calls per ply), of single fused-ply
+    launches and of fused plies replayed from 64-ply hipGraphs, each over the
+    same plies of random play from fresh setups (no auto-reset), at every size
+    in sizes, with the fused engine's tiling autotuned at that size.  Plain and
+    direct fused plies are timed with HIP events around each ply; graph plies
+    by the kernel's own per-ply timestamps."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for n in sizes:
+        eng = E.Engine(n, SEED, K_BATTLELESS, MAX_MOVES, auto_reset=False)
+        obs = eng.obs
+        E.stratego_autotune(eng.ctx, obs, eng.mask, plies=8)
+        G, S = E.stratego_get_tiling(eng.ctx)
+
+        def each(fn):
+            eng.reset()
+            fn()                                   # warm-up ply (first launch of each kernel)
+            eng.reset()
+            xs = []
+            for _ in range(plies):
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                xs.append(e0.elapsed_time(e1))
+            return xs
+
+        def plain_ply():
+            eng.legal_mask()
+            eng.sample()
+            eng.encode()
+            eng.step()
+        plain = each(plain_ply)
+        direct = each(lambda: E.stratego_run_plies(eng.ctx, 1, mask=eng.mask, num_legal=eng.num_legal, obs=obs))
+        ply_ns = torch.empty(GRAPH_PLIES, dtype=torch.int64, device="cuda")
+        run = lambda: E.stratego_run_plies(eng.ctx, GRAPH_PLIES, mask=eng.mask, num_legal=eng.num_legal, obs=obs,
+                                           use_graph=True, ply_ns=ply_ns)
+        eng.reset()
+        run()                                      # graph capture
+        eng.reset()
+        graph, graph_ms = [], 0.0
+        for _ in range(plies // GRAPH_PLIES):
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            e1.synchronize()
+            graph_ms += e0.elapsed_time(e1)
+            graph += [x / 1e6 for x in ply_ns.cpu().tolist()]
+        assert eng.error() == (0, -1)
+        eng.close()
+        res = dict(plain=dict(p50_ms=percentile(plain, 0.5), p99_ms=percentile(plain, 0.99), value=n_rate(n, plain)),
+                   fused_direct=dict(p50_ms=percentile(direct, 0.5), p99_ms=percentile(direct, 0.99),
+                                     value=n_rate(n, direct)),
+                   fused_graph=dict(p50_ms=percentile(graph, 0.5), p99_ms=percentile(graph, 0.99),
+                                    ms_per_ply=graph_ms / (plies // GRAPH_PLIES * GRAPH_PLIES),
+                                    value=n / (graph_ms / (plies // GRAPH_PLIES * GRAPH_PLIES) / 1e3)),
+                   games_per_wg=G, lds_layout=S)
+        out[str(n)] = res
+        print(f"[bench] small batch n={n}: {res}", file=sys.stderr, flush=True)
+    out["workload"] = (f"{plies} plies of random play from fresh setups (no auto-reset) per engine, "
+                       f"mask + sample + both observations + step")
+    return out
+
+
 def n_rate(n, ms_list):
     return n / (sum(ms_list) / len(ms_list) / 1e3)
 
@@ -508,7 +575,7 @@ def main():
                          "(negative: strict arrival order)")
     ap.add_argument("--legs", default=None,
                     help="comma-separated subset of the extra legs to run: rollout_buffer, rules, policies, "
-                         "acting, search, steady (default: all unless --no-extras)")
+                         "acting, search, steady, small (default: all unless --no-extras)")
     ap.add_argument("--no-extras", "--no-history", dest="no_history", action="store_true",
                     help="skip the rollout-buffer, rules, policy, acting-player and search legs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -642,6 +709,8 @@ def main():
     search = search_bench(E, torch) if "search" in legs else None
     torch.cuda.empty_cache()
     steady = steady_state_bench(E, torch, G, S, n) if "steady" in legs else None
+    torch.cuda.empty_cache()
+    small = small_batch_bench(E, torch) if "small" in legs else None
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
@@ -692,6 +761,7 @@ def main():
         "competitive_rules": two_square,
         "policies": policies,
         "search_shaped": search,
+        "small_batches": small,
         "autotune": [dict(games_per_wg=g, lds_layout=s, us_per_ply=u) for g, s, u in tune],
         "cpu_baseline": cpu,
     }
