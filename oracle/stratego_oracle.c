@@ -31,9 +31,11 @@
  *   terminal logic ............ pinned: hand-built positions for every reason
  *   probability channels ...... pinned: brute-force enumeration of consistent assignments
  *                               (known Scouts included), hand-built closed forms
- *   history features .......... parity unpinned by the paper (no worked example);
- *                               checked only by hand-built scenarios derived from
- *                               the written readings, plus invariants
+ *   history features .......... pinned against the readings of App. C.1's words
+ *                               (the paper prints no worked example): a brute
+ *                               force recomputes every ply's increments from the
+ *                               boards before and after the move in whole random
+ *                               games, plus hand-built scenarios
  *   encoding layout ........... pinned: every channel group against planes written
  *                               by hand from the App. C.1 / C.2 tables (both frames,
  *                               move planes most recent first), plus invariants
