@@ -44,7 +44,9 @@
  *                               its convention recomputed for 1024 resamples
  *   two-square rule ........... pinned by hand-built move sequences written
  *                               from the rule's statement (App. A), including
- *                               Scout spans; the Scout case is a reading
+ *                               Scout spans (the Scout case is a reading), and by
+ *                               a brute force that rebuilds each player's run
+ *                               from the move record in random games
  *   chasing rule .............. pinned by hand-built chases written from the
  *                               rule's statement and Table "chase", and by a
  *                               brute force that undoes the whole board
