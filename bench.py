@@ -584,8 +584,8 @@ def main():
                     help="G,L: use this games-per-WG / LDS-layout tiling instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the engine shards games across GPUs with no "
-              "exchange step, so multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: games shard across GPUs with no exchange "
+              "step, so a run on N GPUs is N independent one-GPU runs", file=sys.stderr)
         sys.exit(2)
 
     import torch
