@@ -263,8 +263,8 @@ int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int3
  * only on its record, so it is the same alone and in any mix.  The error word
  * latches E_BAD_STATE for a malformed input record (that game then runs from
  * whatever its slot held).  Synchronises the stream.  Errors: E_INVAL (bad
- * request, a request that can never fit, step requests without obs_out_dev),
- * E_HIP. */
+ * request, a request that can never fit, step requests without obs_out_dev,
+ * a NaN backfill_wait_s), E_HIP. */
 #define STRATEGO_REQ_STEP 0
 #define STRATEGO_REQ_ROLLOUT 1
 typedef struct {
