@@ -57,6 +57,7 @@ struct PlyArgs {
   const int32_t* hist_slot;
   Rules rules;
   int32_t games_per_tile;
+  int32_t tail_from;  // tiles from this one on hold one game each (-1: none)
   int32_t layout;     // observation staging layout in LDS
 };
 
@@ -162,7 +163,13 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   const bool byte_image = encode && ENC == 0;
   if (byte_image) clear_lds(slab + kSlabImage, image_bytes_for(a.layout));
   const int G = a.games_per_tile;
-  const int ntiles = (a.n + G - 1) / G;
+  // tiles below T1 hold G games, the ones from T1 on a single game (with
+  // tickets, the last tiles handed out are single games, so the ply does not
+  // end on a few waves finishing long tiles)
+  const int T1 = a.tail_from >= 0 ? a.tail_from : INT_MAX;
+  const int ntiles = a.tail_from >= 0 ? T1 + (a.n - T1 * G) : (a.n + G - 1) / G;
+  auto tfirst = [&](int t) { return t < T1 ? t * G : T1 * G + (t - T1); };
+  auto tlen = [&](int t) { return t < T1 ? G : 1; };
   // Work distribution: every wave works through tiles of G consecutive games
   // of its own.  With a ticket counter (persistent plies with observations) a
   // wave takes the next tile in address order whenever it becomes free;
@@ -176,7 +183,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   };
   int tile = dynamic ? grab() : (int)blockIdx.x * W + wave;
   int gi = 0;
-  int i = tile < ntiles ? tile * G + gi : a.n;
+  int i = tile < ntiles ? tfirst(tile) + gi : a.n;
   bool have = i < a.n;
   int slot = have ? (a.slots ? uniform_load(a.slots, i) : i) : 0;
   bool slot_ok = have && slot >= 0 && slot < a.total;
@@ -200,7 +207,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     // the next game of this wave (its chunk is grabbed only when needed)
     int ngi = gi + 1, ntile = tile;
     bool need_grab = false;
-    if (ngi >= G || tile * G + ngi >= a.n) {
+    if (ngi >= tlen(tile) || tfirst(tile) + ngi >= a.n) {
       ngi = 0;
       if (dynamic) need_grab = true;
       else ntile += workers;
@@ -213,7 +220,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       if (resolved) return;
       resolved = true;
       if (need_grab) ntile = grab();
-      inext = ntile < ntiles ? ntile * G + ngi : a.n;
+      inext = ntile < ntiles ? tfirst(ntile) + ngi : a.n;
       next_have = inext < a.n;
       if (next_have) {
         next_slot = a.slots ? uniform_load(a.slots, inext) : inext;
@@ -925,6 +932,12 @@ int launch_ply(const DevLimits& d, hipStream_t s, int mode, PlyArgs a, int G, in
     while (tile < 8 && (int64_t)a.n >= 2 * waves * (2 * tile)) tile *= 2;
   }
   a.games_per_tile = tile;
+  a.tail_from = -1;
+  if (persistent && a.tickets != nullptr && tile > 1) {
+    // the last (about) one game per wave is handed out as single-game tiles
+    const int64_t waves = (int64_t)cap * W;
+    a.tail_from = (int)(a.n > waves ? (a.n - waves) / tile : 0);
+  }
   a.layout = S;
   int grid = grid_for(grid_for(a.n, tile), W);
   if (grid > cap) grid = cap;
