@@ -166,10 +166,18 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
   // tiles below T1 hold G games, the ones from T1 on a single game (with
   // tickets, the last tiles handed out are single games, so the ply does not
   // end on a few waves finishing long tiles)
-  const int T1 = a.tail_from >= 0 ? a.tail_from : INT_MAX;
-  const int ntiles = a.tail_from >= 0 ? T1 + (a.n - T1 * G) : (a.n + G - 1) / G;
-  auto tfirst = [&](int t) { return t < T1 ? t * G : T1 * G + (t - T1); };
-  auto tlen = [&](int t) { return t < T1 ? G : 1; };
+  // (only plies with observations take tiles from tickets)
+  constexpr bool kTail = ENC != kEncNone;
+  const int T1 = (kTail && a.tail_from >= 0) ? a.tail_from : INT_MAX;
+  const int ntiles = (kTail && a.tail_from >= 0) ? T1 + (a.n - T1 * G) : (a.n + G - 1) / G;
+  auto tfirst = [&](int t) {
+    if constexpr (kTail) return t < T1 ? t * G : T1 * G + (t - T1);
+    else return t * G;
+  };
+  auto tlen = [&](int t) {
+    if constexpr (kTail) return t < T1 ? G : 1;
+    else return G;
+  };
   // Work distribution: every wave works through tiles of G consecutive games
   // of its own.  With a ticket counter (persistent plies with observations) a
   // wave takes the next tile in address order whenever it becomes free;
