@@ -108,6 +108,20 @@ __device__ __forceinline__ int32_t uniform_load(const int32_t* list, int idx) {
   return ((const __attribute__((address_space(4))) int32_t*)list)[idx];
 }
 
+// The ply kernel's argument block (its only argument, at offset 0 of the
+// argument segment) through an address the compiler cannot carry from one
+// loop iteration to the next.  Pointers a game uses once, for its output rows,
+// are read through it where they are used: one scalar load.  Read through the
+// by-value argument instead, they are hoisted out of the per-game loop, and
+// with scalar registers short the register allocator spills them to vector
+// lanes and reads them back, one vector instruction per 32 bits, on every
+// game.  Only for use inside k_ply.
+__device__ __forceinline__ const __attribute__((address_space(4))) PlyArgs* args_fresh() {
+  uint64_t p = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return (const __attribute__((address_space(4))) PlyArgs*)p;
+}
+
 // A record as two 768-byte halves, 12 bytes per lane: every lane takes part
 // in both accesses, so no branch can skip one.  (A skipped access would leave
 // the compiler unsure which loads are still in flight, and it would then wait
@@ -131,16 +145,19 @@ __device__ __forceinline__ void rec_store(uint8_t* g, const RecRegs& r) {
 }
 
 // A game's mask words and legal-move count.
-__device__ __forceinline__ void store_mask_outputs(const PlyArgs& a, int oi, const uint64_t w[3], int n,
-                                                   bool with_mask) {
+__device__ __forceinline__ void store_mask_outputs(int oi, const uint64_t w[3], int n, bool with_mask) {
   const int lane = lane_id();
-  if (with_mask && a.mask) {
-    uint64_t* m = a.mask + (size_t)oi * kMaskWords;
+  uint64_t* const mask = args_fresh()->mask;
+  if (with_mask && mask) {
+    uint64_t* m = mask + (size_t)oi * kMaskWords;
 #pragma unroll
     for (int g = 0; g < 3; ++g)
       if (lane + 64 * g < kMaskWords) m[lane + 64 * g] = w[g];
   }
-  if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
+  if (lane == 0) {
+    int16_t* const num_legal = args_fresh()->num_legal;
+    if (num_legal) num_legal[oi] = (int16_t)n;
+  }
 }
 
 // FAST: the fused ply's register-board path (drawn actions, neither
@@ -282,7 +299,8 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     } else {
       uint8_t* R = slab + cur;
       uint8_t* gstate = a.states + (size_t)slot * kRecordBytes;
-      const int oi = a.out_index ? uniform_load(a.out_index, i) : i;
+      const int32_t* const out_index = args_fresh()->out_index;
+      const int oi = out_index ? uniform_load(out_index, i) : i;
       int action = -1;
       SquareRegs rg;
       uint64_t w[3];
@@ -348,8 +366,11 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       }
       park_next();
       if (kDefer && (MODE & kDoMask)) {   // this game's mask outputs, behind the park
-        store_mask_outputs(a, oi, w, n, !NOMASK);
-        if ((MODE & kDoSample) && a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
+        store_mask_outputs(oi, w, n, !NOMASK);
+        if ((MODE & kDoSample) && lane == 0) {
+          int16_t* const actions_out = args_fresh()->actions_out;
+          if (actions_out) actions_out[(size_t)a.out_base + oi] = (int16_t)action;
+        }
       }
       if (MODE & kStepFromInput) action = a.actions_in[i];
       if (encode) {
@@ -360,18 +381,24 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
         else encode_game_bytes(R, slab, a.rules, segments_of(a.layout), out);
       }
       if (MODE & kDoStep) {
-        if (a.hist) store_record(a.hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
+        uint8_t* const hist = args_fresh()->hist;
+        if (hist) store_record(hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
         StepOut o = FAST ? fast_step_game(R, slab + kSlabScratch, slab + kSlabProbQ, a.rules, action, rg)
                          : step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, slab + kSlabProbQ,
                                                                     a.rules, action);
         const size_t row = (size_t)a.out_base + oi;
         if (lane == 0) {
-          if (a.done) a.done[row] = (int8_t)o.done;
-          if (a.outcome) a.outcome[row] = (int8_t)o.outcome;
-          if (a.reason) a.reason[row] = (uint8_t)o.reason;
-          if (a.ep_len) a.ep_len[row] = (int16_t)o.ep_len;
-          if (o.illegal) atomicMin(&a.err[0], slot);
-          if (a.hist) a.hist_steps[hist_row + slot] = pack_step(action, o);
+          const auto* f = args_fresh();
+          int8_t* const done_p = f->done;
+          int8_t* const outcome_p = f->outcome;
+          uint8_t* const reason_p = f->reason;
+          int16_t* const ep_len_p = f->ep_len;
+          if (done_p) done_p[row] = (int8_t)o.done;
+          if (outcome_p) outcome_p[row] = (int8_t)o.outcome;
+          if (reason_p) reason_p[row] = (uint8_t)o.reason;
+          if (ep_len_p) ep_len_p[row] = (int16_t)o.ep_len;
+          if (o.illegal) atomicMin(&f->err[0], slot);
+          if (f->hist) f->hist_steps[hist_row + slot] = pack_step(action, o);
         }
         wave_sync();
         if (kDefer) {
