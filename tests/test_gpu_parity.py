@@ -230,6 +230,45 @@ def test_observation_free_plies_at_ragged_sizes(n):
     eng.close()
 
 
+@pytest.mark.parametrize("n,with_mask", [(65, True), (5121, True), (1000, False)])
+def test_observation_free_plies_write_every_output(n, with_mask):
+    """Plies without observations, in the variant the rollouts use, with every
+    per-game output asked for: the legal mask (or, without one, the legal
+    count alone), action, done, outcome, reason and episode length equal the
+    oracle's on every ply, one ply per call and from a graph of 32 plies.
+    Short games (k = 20, 40 moves) make auto-resets and every end reason
+    frequent."""
+    seed = 71 + n
+    eng = E.Engine(n, seed, k_battleless=20, max_moves=40, auto_reset=True)
+    ref = O.OracleEngine(n, seed, k_battleless=20, max_moves=40, auto_reset=True)
+    mask = eng.mask if with_mask else None
+    keys = ("done", "outcome", "reason", "ep_len")
+    ended = 0
+    for ply in range(12):
+        E.stratego_run_plies(eng.ctx, 1, mask=mask, num_legal=eng.num_legal, actions=eng.actions,
+                             **{k: getattr(eng, k) for k in keys})
+        r = ref.ply(obs=False, mask=with_mask)
+        if with_mask:
+            assert_same(f"mask@{ply}", cpu(mask), r["mask"])
+        for k in ("num_legal", "actions") + keys:
+            assert_same(f"{k}@{ply}", cpu(getattr(eng, k)), r[k])
+    P = 32
+    rows = {k: torch.full((P, n), -7, dtype=getattr(eng, k).dtype, device="cuda") for k in ("actions",) + keys}
+    E.stratego_run_plies(eng.ctx, P, mask=mask, num_legal=eng.num_legal, use_graph=True, **rows)
+    for p in range(P):
+        r = ref.ply(obs=False, mask=with_mask)
+        for k in ("actions",) + keys:
+            assert_same(f"{k}@graph.{p}", cpu(rows[k][p]), r[k])
+        ended += int((r["done"] != 0).sum())
+    if with_mask:
+        assert_same("mask@last", cpu(mask), r["mask"])
+    assert_same("num_legal@last", cpu(eng.num_legal), r["num_legal"])
+    assert_same("states", cpu(eng.export()), ref.export())
+    assert ended > 0
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
 # ---------------------------------------------------------------- imported states
 def random_position_records(count, seed=0):
     from test_oracle_pins import random_position
