@@ -723,14 +723,14 @@ __device__ __forceinline__ int sample_from_words(const uint64_t w[3], int n, uin
 // (zero beyond 99).  Same Philox block as the uniform sampler: r1 =
 // bounded(y, P) picks the r1-th square with a legal move in ascending
 // order, r2 = bounded(z, m) its r2-th destination.  -1 without moves.
-__device__ __forceinline__ int sample_magnet(uint64_t lo0, uint64_t hi0, uint64_t lo1, uint64_t hi1,
-                                             uint64_t seed, uint32_t game_id, uint32_t ply,
-                                             uint32_t episode) {
+// draw() gives the block, and is called only when there is a legal move.
+template <class Draw>
+__device__ __forceinline__ int sample_magnet(uint64_t lo0, uint64_t hi0, uint64_t lo1, uint64_t hi1, Draw draw) {
   const int lane = lane_id();
   const uint64_t has0 = ballot((lo0 | hi0) != 0), has1 = ballot((lo1 | hi1) != 0);
   const int c0 = __popcll(has0), P = c0 + __popcll(has1);
   if (P == 0) return -1;
-  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  const uint4 u = draw();
   const int r1 = (int)mulshift(u.y, (uint32_t)P);
   const int x = r1 < c0 ? select_bit(has0, r1) : 64 + select_bit(has1, r1 - c0);
   const int src = x & 63;
@@ -741,6 +741,12 @@ __device__ __forceinline__ int sample_magnet(uint64_t lo0, uint64_t hi0, uint64_
   const int y = r2 < nlo ? select_bit(lo, r2) : 64 + select_bit(hi, r2 - nlo);
   (void)lane;
   return 100 * x + y;
+}
+
+__device__ __forceinline__ int sample_magnet(uint64_t lo0, uint64_t hi0, uint64_t lo1, uint64_t hi1,
+                                             uint64_t seed, uint32_t game_id, uint32_t ply,
+                                             uint32_t episode) {
+  return sample_magnet(lo0, hi0, lo1, hi1, [&] { return philox(make_uint4(game_id, ply, episode, 0u), seed); });
 }
 
 // The 100-bit destination set of square x from packed mask words (global).
@@ -1300,10 +1306,12 @@ __device__ __forceinline__ int total_count(const uint32_t pk[2]) {
 
 // Uniform legal action (as sample_from_words: the r-th legal action in
 // ascending action order) from the counts.
-__device__ __forceinline__ int sample_counts(const uint32_t pk[2], int n, uint64_t seed, uint32_t game_id,
-                                             uint32_t ply, uint32_t episode) {
+// draw() gives the Philox block of the move counter, and is called only when
+// there is a legal move.
+template <class Draw>
+__device__ __forceinline__ int sample_counts(const uint32_t pk[2], int n, Draw draw) {
   if (n <= 0) return -1;
-  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  const uint4 u = draw();
   int r = (int)mulshift(u.x, (uint32_t)n);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -1322,12 +1330,12 @@ __device__ __forceinline__ int sample_counts(const uint32_t pk[2], int n, uint64
 }
 
 // Magnet policy sample (as sample_magnet) from the counts.
-__device__ __forceinline__ int magnet_counts(const uint32_t pk[2], uint64_t seed, uint32_t game_id, uint32_t ply,
-                                             uint32_t episode) {
+template <class Draw>
+__device__ __forceinline__ int magnet_counts(const uint32_t pk[2], Draw draw) {
   const uint64_t has0 = ballot(pk[0] != 0), has1 = ballot(pk[1] != 0);
   const int c0 = __popcll(has0), P = c0 + __popcll(has1);
   if (P == 0) return -1;
-  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  const uint4 u = draw();
   const int r1 = (int)mulshift(u.y, (uint32_t)P);
   const int x = r1 < c0 ? select_bit(has0, r1) : 64 + select_bit(has1, r1 - c0);
   const uint32_t pkx = (uint32_t)__builtin_amdgcn_readlane((int)(x < 64 ? pk[0] : pk[1]), x & 63);
@@ -1343,10 +1351,10 @@ __device__ __forceinline__ int count_dests(const uint64_t d[4]) {
 // Uniform legal action (as sample_from_words: the r-th legal action in
 // ascending action order, r = bounded(x, n) of the move counter) from the
 // destination sets: squares in ascending order, then destinations.
-__device__ __forceinline__ int sample_dests(const uint64_t d[4], int n, uint64_t seed, uint32_t game_id,
-                                            uint32_t ply, uint32_t episode) {
+template <class Draw>
+__device__ __forceinline__ int sample_dests(const uint64_t d[4], int n, Draw draw) {
   if (n <= 0) return -1;
-  const uint4 u = philox(make_uint4(game_id, ply, episode, 0u), seed);
+  const uint4 u = draw();
   int r = (int)mulshift(u.x, (uint32_t)n);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {

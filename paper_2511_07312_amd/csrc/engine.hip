@@ -207,6 +207,31 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     return __shfl(t, 0, 64);
   };
   int tile = dynamic ? grab() : (int)blockIdx.x * W + wave;
+  // Observation-free plies draw their actions ahead.  Games are split
+  // statically, so a wave knows which games it will take, and a launch steps
+  // each game once, from the counter (game id, ply, episode) its record holds
+  // when the launch starts.  Lane j computes the generator's block for the
+  // wave's j-th game: one pass on the vector unit covers 64 games, where a
+  // pass per game on the scalar unit was ten rounds of multiplies each.  A
+  // wave's games beyond the 64th draw in the loop as before.  (The counters
+  // are read while no store is in flight, at the top of the launch.)
+  constexpr bool kAhead = ENC == kEncNone && FAST;
+  uint4 ahead = make_uint4(0u, 0u, 0u, 0u);   // words x, y, z of this lane's game
+  int kcur = 0;                               // this wave's games so far
+  if constexpr (kAhead) {
+    const int t = tile + (lane / G) * workers;
+    const int ii = t < ntiles ? t * G + lane % G : a.n;
+    uint4 c = make_uint4(0u, 0u, 0u, 0u);
+    if (ii < a.n) {
+      const int sl = a.slots ? a.slots[ii] : ii;
+      if (sl >= 0 && sl < a.total) {
+        const uint4 h = *reinterpret_cast<const uint4*>(a.states + (size_t)sl * kRecordBytes);
+        static_assert(kOffGameId == 0 && kOffEpisode == 4 && kOffPly == 8, "the counter is the header's first words");
+        c = make_uint4(h.x, h.z, h.y, 0u);   // game id, ply, episode
+      }
+    }
+    ahead = philox(c, a.rules.seed);
+  }
   int gi = 0;
   int i = tile < ntiles ? tfirst(tile) + gi : a.n;
   bool have = i < a.n;
@@ -337,15 +362,30 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
         if (FAST && (MODE & kDoSample)) {
           // wave-uniform copies, so that the generator and the selection run
           // on the scalar unit
-          const uint32_t gid = uniform_u32(hdr_u32(R, kOffGameId)), ply = uniform_u32(hdr_u32(R, kOffPly)),
-                         ep = uniform_u32(hdr_u32(R, kOffEpisode));
+          uint32_t gid = 0, ply = 0, ep = 0;
+          if constexpr (!kAhead) {
+            gid = uniform_u32(hdr_u32(R, kOffGameId));
+            ply = uniform_u32(hdr_u32(R, kOffPly));
+            ep = uniform_u32(hdr_u32(R, kOffEpisode));
+          }
+          auto draw = [&]() -> uint4 {
+            if constexpr (kAhead) {
+              if (kcur < 64)
+                return make_uint4((uint32_t)__builtin_amdgcn_readlane((int)ahead.x, kcur),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)ahead.y, kcur),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)ahead.z, kcur), 0u);
+              return philox(make_uint4(uniform_u32(hdr_u32(R, kOffGameId)), uniform_u32(hdr_u32(R, kOffPly)),
+                                       uniform_u32(hdr_u32(R, kOffEpisode)), 0u),
+                            a.rules.seed);
+            } else {
+              return philox(make_uint4(gid, ply, ep, 0u), a.rules.seed);
+            }
+          };
           const bool magnet = a.rules.sampler == kSamplerMagnet;
           if (!NOMASK && a.mask)
-            action = magnet ? (n == 0 ? -1 : sample_magnet(d[0], d[1], d[2], d[3], a.rules.seed, gid, ply, ep))
-                            : sample_dests(d, n, a.rules.seed, gid, ply, ep);
+            action = magnet ? (n == 0 ? -1 : sample_magnet(d[0], d[1], d[2], d[3], draw)) : sample_dests(d, n, draw);
           else
-            action = magnet ? (n == 0 ? -1 : magnet_counts(pk, a.rules.seed, gid, ply, ep))
-                            : sample_counts(pk, n, a.rules.seed, gid, ply, ep);
+            action = magnet ? (n == 0 ? -1 : magnet_counts(pk, draw)) : sample_counts(pk, n, draw);
           if (!kDefer && a.actions_out && lane == 0) a.actions_out[(size_t)a.out_base + oi] = (int16_t)action;
         } else if (MODE & kDoSample) {
           if (a.rules.sampler == kSamplerMagnet) {
@@ -413,6 +453,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
     i = inext;
     tile = ntile;
     gi = ngi;
+    ++kcur;
     slot = next_slot;
     slot_ok = next_ok;
     have = next_have;

@@ -230,6 +230,26 @@ def test_observation_free_plies_at_ragged_sizes(n):
     eng.close()
 
 
+@pytest.mark.parametrize("sampler", [E.SAMPLER_UNIFORM, E.SAMPLER_MAGNET])
+def test_observation_free_plies_beyond_64_games_per_wave(sampler):
+    """Observation-free plies draw a wave's first 64 games ahead, one game per
+    lane, and later games in the loop.  At 600,000 games a persistent launch
+    gives every wave more than 64 games (256 CUs hold at most 8192 waves of
+    this kernel), so both kinds of draw occur: every ply's actions and the
+    final records equal the oracle's."""
+    n, seed, plies = 600_000, 41, 3
+    eng = E.Engine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True, sampler=sampler)
+    ref = O.OracleEngine(n, seed, k_battleless=100, max_moves=1000, auto_reset=True, sampler=sampler)
+    acts = torch.empty((plies, n), dtype=torch.int16, device="cuda")
+    E.stratego_run_plies(eng.ctx, plies, actions=acts)
+    for p in range(plies):
+        r = ref.ply(obs=False, mask=False)
+        assert_same(f"actions@{p}", cpu(acts[p]), r["actions"])
+    assert_same("states", cpu(eng.export()), ref.export())
+    assert eng.error() == (0, -1)
+    eng.close()
+
+
 @pytest.mark.parametrize("n,with_mask", [(65, True), (5121, True), (1000, False)])
 def test_observation_free_plies_write_every_output(n, with_mask):
     """Plies without observations, in the variant the rollouts use, with every
