@@ -2228,49 +2228,87 @@ __device__ __forceinline__ ResampleSource resample_prepare(const uint8_t* R) {
   return S;
 }
 
-// One resample of S with game id new_id, stored as a record at out.
-__device__ __forceinline__ void resample_store(const ResampleSource& S, uint64_t seed, uint32_t new_id,
-                                               uint8_t* out) {
+// Resamples of one source, one per lane: lane r draws resample r with game id
+// id0 + r, and the wave then stores the first cnt of them as records at
+// out, out + 1536, ...  A lane keeps its own copies of the source's unmoved
+// list and type list in LDS rows (um + r * kUmStride, ls + r * kLsStride,
+// odd strides, so a column and a row both fall in distinct banks) and shuffles
+// them with its own words of the stream (new id, block, episode, tag 3): word
+// m is word m mod 4 of block m / 4.  Words 0 .. I-1 draw the immovable
+// pieces among the unmoved ones (a partial shuffle from the front), words
+// I .. I+L-2 shuffle the movable multiset from the back, as the oracle does.
+constexpr int kUmStride = 41, kLsStride = 33;   // at least 40 unmoved pieces and 33 movable types
+constexpr int kResampleRowsBytes = 64 * (kUmStride + kLsStride) * 4;
+
+__device__ __forceinline__ void resample_wave(const ResampleSource& S, uint64_t seed, uint32_t id0, int cnt,
+                                              int32_t* um, int32_t* ls, uint8_t* out) {
   const int lane = lane_id();
-  // word m of the stream, one per lane; the immovable draws take words
-  // 0 .. I-1, the movable shuffle (i = L-1 down to 1) words I .. I+L-2
-  const uint4 blk = philox(make_uint4(new_id, (uint32_t)(lane >> 2), S.episode, 3u), seed);
-  const int q = lane & 3;
-  const uint32_t word = q == 0 ? blk.x : q == 1 ? blk.y : q == 2 ? blk.z : blk.w;
-  int jv = 0;
-  if (lane < S.I) jv = lane + (int)mulshift(word, (uint32_t)(S.nu - lane));
-  else if (lane < S.I + S.L - 1) jv = (int)mulshift(word, (uint32_t)(S.L - (lane - S.I)));
-  int um = S.unmoved, ls = S.list;
-  for (int a = 0; a < S.I; ++a) um = lane_swap(um, a, __builtin_amdgcn_readlane(jv, a));
-  for (int s = 0; s < S.L - 1; ++s)
-    ls = lane_swap(ls, S.L - 1 - s, __builtin_amdgcn_readlane(jv, S.I + s));
-  // the chosen immovable pieces
-  uint64_t chosen = 0;
-  for (int a = 0; a < S.I; ++a) chosen |= 1ull << (__builtin_amdgcn_readlane(um, a) - 40 * S.z);
-  const uint64_t rest = S.hidden & ~chosen;
-  // chunk lane holds piece lane - 16 (lanes 16..63), chunk 64 + lane piece 48 + lane (lanes 0..31)
-  int newtype[2];
+  int32_t* my_um = um + lane * kUmStride;
+  int32_t* my_ls = ls + lane * kLsStride;
+  for (int e = 0; e < S.nu; ++e) my_um[e] = __builtin_amdgcn_readlane(S.unmoved, e);
+  for (int e = 0; e < S.L; ++e) my_ls[e] = __builtin_amdgcn_readlane(S.list, e);
+  const uint32_t new_id = id0 + (uint32_t)lane;
+  const int ndraw = S.I + (S.L > 0 ? S.L - 1 : 0);
+  for (int b = 0; 4 * b < ndraw; ++b) {
+    const uint4 blk = philox(make_uint4(new_id, (uint32_t)b, S.episode, 3u), seed);
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int id = h == 0 ? lane - 16 : 48 + lane;
-    const int m = id - 40 * S.z;
-    const bool ours = (h == 0 ? lane >= 16 : lane < 32) && m >= 0 && m < 40;
-    const int mm = ours ? m : 0;
-    const int rank = __popcll(rest & ((1ull << mm) - 1ull));
-    const int from_list = __shfl(ls, rank, 64);
-    int t = -1;
-    if (ours && ((rest >> mm) & 1ull)) t = from_list;
-    for (int a = 0; a < S.I; ++a)
-      if (ours && __builtin_amdgcn_readlane(um, a) == id) t = a < S.nflag ? kFlag : kBomb;
-    newtype[h] = t;
+    for (int q = 0; q < 4; ++q) {
+      const int m = 4 * b + q;
+      if (m >= ndraw) break;
+      const uint32_t word = q == 0 ? blk.x : q == 1 ? blk.y : q == 2 ? blk.z : blk.w;
+      int32_t* row;
+      int x, y;
+      if (m < S.I) {
+        row = my_um;
+        x = m;
+        y = m + (int)mulshift(word, (uint32_t)(S.nu - m));
+      } else {
+        const int k = m - S.I;
+        row = my_ls;
+        x = S.L - 1 - k;
+        y = (int)mulshift(word, (uint32_t)(S.L - k));
+      }
+      const int32_t vx = row[x], vy = row[y];
+      row[x] = vy;
+      row[y] = vx;
+    }
   }
-  uint4 c0 = S.c0, c1 = S.c1;
-  if (newtype[0] >= 0) c0.x = (c0.x & ~15u) | (uint32_t)newtype[0];
-  if (newtype[1] >= 0) c1.x = (c1.x & ~15u) | (uint32_t)newtype[1];
-  if (lane == 0) c0.x = new_id;   // header word 0: the game id
-  uint4* dst = reinterpret_cast<uint4*>(out);
-  dst[lane] = c0;
-  if (lane < 32) dst[64 + lane] = c1;
+  // this lane's immovable pieces: the first nflag of the drawn ones are Flags,
+  // the rest Bombs (bit m: piece 40 z + m)
+  uint64_t fl = 0, bm = 0;
+  for (int a = 0; a < S.I; ++a) {
+    const uint64_t bit = 1ull << (my_um[a] - 40 * S.z);
+    if (a < S.nflag) fl |= bit;
+    else bm |= bit;
+  }
+  // chunk lane holds piece lane - 16 (lanes 16..63), chunk 64 + lane piece 48 + lane (lanes 0..31)
+  for (int r = 0; r < cnt; ++r) {
+    const uint64_t f = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(fl >> 32), r) << 32) |
+                       (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)fl, r);
+    const uint64_t b = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bm >> 32), r) << 32) |
+                       (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bm, r);
+    const uint64_t rest = S.hidden & ~(f | b);
+    const int32_t* types = ls + r * kLsStride;
+    uint4 c[2] = {S.c0, S.c1};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int id = h == 0 ? lane - 16 : 48 + lane;
+      const int m = id - 40 * S.z;
+      const bool ours = (h == 0 ? lane >= 16 : lane < 32) && m >= 0 && m < 40;
+      const int mm = ours ? m : 0;
+      int t = -1;
+      if (ours) {
+        if ((rest >> mm) & 1ull) t = types[__popcll(rest & ((1ull << mm) - 1ull))];
+        else if ((f >> mm) & 1ull) t = kFlag;
+        else if ((b >> mm) & 1ull) t = kBomb;
+      }
+      if (t >= 0) c[h].x = (c[h].x & ~15u) | (uint32_t)t;
+    }
+    if (lane == 0) c[0].x = id0 + (uint32_t)r;   // header word 0: the game id
+    uint4* dst = reinterpret_cast<uint4*>(out + (size_t)r * kRecordBytes);
+    dst[lane] = c[0];
+    if (lane < 32) dst[64 + lane] = c[1];
+  }
 }
 
 // ---------------------------------------------------------------- validation

@@ -535,31 +535,32 @@ __global__ void __launch_bounds__(256) k_import(uint8_t* states, const int32_t* 
 }
 
 // Slot k = i*per + j receives a resample of source record i.  Each wave takes
-// up to kResamplesPerWave consecutive resamples of one source: it loads and
-// checks the source once, then draws and stores its resamples.
-constexpr int kResamplesPerWave = 16;
-__global__ void __launch_bounds__(256) k_resample(uint8_t* states, const uint8_t* src, int32_t nsrc,
-                                                 int32_t per, uint64_t seed, uint32_t id_base,
-                                                 int32_t* err) {
+// up to 64 consecutive resamples of one source, one per lane: it loads and
+// checks the source once, draws the resamples in its lanes, then stores them.
+constexpr int kResamplesPerWave = 64;
+constexpr int kResampleWaves = 2;   // waves per workgroup
+constexpr int kResampleWaveBytes = kRecordBytes + kResampleRowsBytes;
+__global__ void __launch_bounds__(64 * kResampleWaves) k_resample(uint8_t* states, const uint8_t* src,
+                                                                 int32_t nsrc, int32_t per, uint64_t seed,
+                                                                 uint32_t id_base, int32_t* err) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
   const int chunks = (per + kResamplesPerWave - 1) / kResamplesPerWave;
-  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  const int64_t w = (int64_t)blockIdx.x * kResampleWaves + wave;
   if (w >= (int64_t)nsrc * chunks) return;
   const int i = (int)(w / chunks);
   const int j0 = (int)(w % chunks) * kResamplesPerWave;
-  const int j1 = j0 + kResamplesPerWave < per ? j0 + kResamplesPerWave : per;
-  uint8_t* R = smem + wave * kRecordBytes;
+  const int cnt = per - j0 < kResamplesPerWave ? per - j0 : kResamplesPerWave;
+  uint8_t* R = smem + wave * kResampleWaveBytes;
+  int32_t* um = reinterpret_cast<int32_t*>(R + kRecordBytes);
   load_record(R, src + (size_t)i * kRecordBytes);
   if (!record_ok(R)) {
     if (lane_id() == 0) atomicMin(&err[1], i * per + j0);
     return;
   }
   const ResampleSource S = resample_prepare(R);
-  for (int j = j0; j < j1; ++j) {
-    const int k = i * per + j;
-    resample_store(S, seed, id_base + (uint32_t)k, states + (size_t)k * kRecordBytes);
-  }
+  const int k0 = i * per + j0;
+  resample_wave(S, seed, id_base + (uint32_t)k0, cnt, um, um + 64 * kUmStride, states + (size_t)k0 * kRecordBytes);
 }
 
 // Copy the records of the listed slots to out (contiguous).
@@ -1507,7 +1508,9 @@ int stratego_reset_resampled(stratego_ctx* c, const void* src, int32_t nsrc, int
   if (!c || !src || nsrc <= 0 || per <= 0 || (int64_t)nsrc * per > c->cfg.num_games)
     return STRATEGO_E_INVAL;
   const int64_t waves = (int64_t)nsrc * ((per + kResamplesPerWave - 1) / kResamplesPerWave);
-  hipLaunchKernelGGL(k_resample, dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * kRecordBytes, c->stream,
+  if ((size_t)kResampleWaves * kResampleWaveBytes > c->max_lds) return STRATEGO_E_INVAL;
+  hipLaunchKernelGGL(k_resample, dim3((unsigned)((waves + kResampleWaves - 1) / kResampleWaves)),
+                     dim3(64 * kResampleWaves), kResampleWaves * kResampleWaveBytes, c->stream,
                      c->states, reinterpret_cast<const uint8_t*>(src), nsrc, per, c->cfg.seed, game_id_base,
                      c->err);
   return hipGetLastError() == hipSuccess ? STRATEGO_OK : STRATEGO_E_HIP;
