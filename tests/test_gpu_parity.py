@@ -454,6 +454,25 @@ def test_resample_edge_cases():
     eng.close()
 
 
+@pytest.mark.parametrize("per", [1, 64, 65, 129])
+def test_resample_chunk_boundaries(per):
+    """A wave draws up to 64 resamples of one source, one per lane: per
+    around that chunk (a single resample, exactly one chunk, one chunk and a
+    single resample, two chunks and one) gives the oracle's records."""
+    seed, base = 19, 77
+    ref = O.OracleEngine(40, 8, auto_reset=True)
+    for _ in range(57):
+        ref.ply(obs=False, mask=False)
+    src = np.concatenate([O.OracleEngine(3, 9).export(), ref.export()])
+    n = len(src) * per
+    eng = E.Engine(n, seed)
+    E.stratego_reset_resampled(eng.ctx, torch.from_numpy(src).cuda(), per, base)
+    assert eng.error() == (0, -1)
+    want = O.OracleEngine.from_records(src, seed).resample(per, seed, base).export()
+    assert_same(f"resampled, per {per}", cpu(eng.export()), want)
+    eng.close()
+
+
 def test_resample_then_magnet_rollouts():
     """The search-shaped load with magnet-policy rollouts (section 2.4): 64
     mid-game states x 16 resamples, 50 plies in a captured graph, every
