@@ -360,8 +360,8 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
           if (a.num_legal && lane == 0) a.num_legal[oi] = (int16_t)n;
         }
         if (FAST && (MODE & kDoSample)) {
-          // wave-uniform copies, so that the generator and the selection run
-          // on the scalar unit
+          // wave-uniform copies of the counter, so that the generator (unless
+          // the draw was taken ahead) and the selection run on the scalar unit
           uint32_t gid = 0, ply = 0, ep = 0;
           if constexpr (!kAhead) {
             gid = uniform_u32(hdr_u32(R, kOffGameId));
