@@ -1575,12 +1575,13 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
   pend_free[0].reserve(N);
   pend_free[1].reserve(N);
   for (int i = 0; i < N; ++i) free_now.push_back(N - 1 - i);
-  int32_t *h_adm[2], *h_step[2], *h_roll[2], *h_oidx[2], *d_adm[2], *d_step[2], *d_roll[2], *d_oidx[2];
+  int32_t *h_adm[2], *h_run[2], *d_adm[2], *d_run[2];
   for (int b = 0; b < 2; ++b) {
     int32_t* hb = c->srv_host + (size_t)b * 4 * N;
     int32_t* db = c->srv_dev + (size_t)b * 4 * N;
-    h_adm[b] = hb; h_step[b] = hb + N; h_roll[b] = hb + 2 * (size_t)N; h_oidx[b] = hb + 3 * (size_t)N;
-    d_adm[b] = db; d_step[b] = db + N; d_roll[b] = db + 2 * (size_t)N; d_oidx[b] = db + 3 * (size_t)N;
+    // admitted slots (N), then the iteration's lists packed in one run (up to 2 N)
+    h_adm[b] = hb; h_run[b] = hb + N;
+    d_adm[b] = db; d_run[b] = db + N;
   }
   hipEvent_t ev_ref = nullptr, ev_first = nullptr, ev_start[2] = {}, ev_end[2] = {}, ev_import[2] = {};
   bool ev_ok = hipEventCreate(&ev_ref) == hipSuccess && hipEventCreate(&ev_first) == hipSuccess;
@@ -1695,27 +1696,33 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
     // 3. one fused ply for every active game: step requests with
     //    observations, rollout requests without
     int nstep = 0, nroll = 0;
-    for (int r : active) {
-      const stratego_request& q = reqs[r];
-      const int32_t* sl = slot_store.data() + seg[r];
-      if (q.kind == STRATEGO_REQ_STEP) {
-        run_off[r] = nstep;
-        for (int j = 0; j < q.num_games; ++j) {
-          h_step[b][nstep + j] = sl[j];
-          h_oidx[b][nstep + j] = obs_by_slot ? sl[j] : q.first + j;
+    for (int r : active) (reqs[r].kind == STRATEGO_REQ_STEP ? nstep : nroll) += reqs[r].num_games;
+    // one copy: step slots, their output rows, then rollout slots
+    int32_t* hs = h_run[b];
+    int32_t *ho = hs + nstep, *hr = hs + 2 * nstep;
+    int32_t* ds = d_run[b];
+    int32_t *d_rows = ds + nstep, *d_rl = ds + 2 * nstep;
+    {
+      int is = 0, ir = 0;
+      for (int r : active) {
+        const stratego_request& q = reqs[r];
+        const int32_t* sl = slot_store.data() + seg[r];
+        if (q.kind == STRATEGO_REQ_STEP) {
+          run_off[r] = is;
+          for (int j = 0; j < q.num_games; ++j) {
+            hs[is + j] = sl[j];
+            ho[is + j] = obs_by_slot ? sl[j] : q.first + j;
+          }
+          is += q.num_games;
+        } else {
+          run_off[r] = ir;
+          for (int j = 0; j < q.num_games; ++j) hr[ir + j] = sl[j];
+          ir += q.num_games;
         }
-        nstep += q.num_games;
-      } else {
-        run_off[r] = nroll;
-        for (int j = 0; j < q.num_games; ++j) h_roll[b][nroll + j] = sl[j];
-        nroll += q.num_games;
       }
     }
-    if ((nstep > 0 &&
-         (hipMemcpyAsync(d_step[b], h_step[b], nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-          hipMemcpyAsync(d_oidx[b], h_oidx[b], nstep * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)) ||
-        (nroll > 0 &&
-         hipMemcpyAsync(d_roll[b], h_roll[b], nroll * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)) {
+    if (hipMemcpyAsync(ds, hs, (size_t)(2 * nstep + nroll) * sizeof(int32_t), hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess) {
       rc = STRATEGO_E_HIP;
       break;
     }
@@ -1723,16 +1730,16 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
     if (iterations == 0 && hipEventRecord(ev_first, c->stream) != hipSuccess) { rc = STRATEGO_E_HIP; break; }
     if (nstep > 0) {
       PlyArgs a = base_args(c);
-      a.slots = d_step[b];
+      a.slots = ds;
       a.n = nstep;
-      a.out_index = d_oidx[b];
+      a.out_index = d_rows;
       a.obs = obs_out;
       rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
       if (rc != STRATEGO_OK) break;
     }
     if (nroll > 0) {
       PlyArgs a = base_args(c);
-      a.slots = d_roll[b];
+      a.slots = d_rl;
       a.n = nroll;
       rc = launch_ply(c, c->stream, kFused, a, c->G, c->S, true);
       if (rc != STRATEGO_OK) break;
@@ -1745,7 +1752,7 @@ int stratego_serve(stratego_ctx* c, const stratego_request* reqs, int32_t nreq, 
       const int r = active[ai];
       if (--remaining[r] > 0) { active[keep++] = r; continue; }
       const stratego_request& q = reqs[r];
-      const int32_t* list = (q.kind == STRATEGO_REQ_STEP ? d_step[b] : d_roll[b]) + run_off[r];
+      const int32_t* list = (q.kind == STRATEGO_REQ_STEP ? ds : d_rl) + run_off[r];
       hipLaunchKernelGGL(k_gather, dim3(grid_for(q.num_games, 4)), dim3(256), 0, c->stream, c->states, list,
                          q.num_games, out + (size_t)q.first * kRecordBytes);
       finishing[b].push_back(r);
