@@ -230,7 +230,7 @@ int stratego_run_plies_slots(stratego_ctx* ctx, const int32_t* slots_dev, int32_
  * they are.  A malformed source record latches E_BAD_STATE with the slot of
  * its first resample (i*per) and its slots are left as they are.  Errors:
  * E_INVAL (null source, nsrc or per below 1, nsrc*per above N, a device with
- * less than 40 KB of LDS per workgroup), E_HIP. */
+ * less than 80 KB of LDS per workgroup), E_HIP. */
 int stratego_reset_resampled(stratego_ctx* ctx, const void* src_states_dev, int32_t nsrc,
                              int32_t per, uint32_t game_id_base);
 

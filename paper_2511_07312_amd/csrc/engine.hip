@@ -538,7 +538,7 @@ __global__ void __launch_bounds__(256) k_import(uint8_t* states, const int32_t* 
 // up to 64 consecutive resamples of one source, one per lane: it loads and
 // checks the source once, draws the resamples in its lanes, then stores them.
 constexpr int kResamplesPerWave = 64;
-constexpr int kResampleWaves = 2;   // waves per workgroup
+constexpr int kResampleWaves = 4;   // waves per workgroup
 constexpr int kResampleWaveBytes = kRecordBytes + kResampleRowsBytes;
 __global__ void __launch_bounds__(64 * kResampleWaves) k_resample(uint8_t* states, const uint8_t* src,
                                                                  int32_t nsrc, int32_t per, uint64_t seed,
