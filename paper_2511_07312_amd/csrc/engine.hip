@@ -122,6 +122,24 @@ __device__ __forceinline__ const __attribute__((address_space(4))) PlyArgs* args
   return (const __attribute__((address_space(4))) PlyArgs*)p;
 }
 
+// The rules, read field by field through args_fresh (a struct copy out of
+// the constant address space has no constructor).  Observation-free plies
+// read them per game: held for the whole launch, they pushed other scalar
+// values into spills.
+__device__ __forceinline__ Rules rules_fresh() {
+  const auto* f = args_fresh();
+  Rules r;
+  r.seed = f->rules.seed;
+  r.k_battleless = f->rules.k_battleless;
+  r.max_moves = f->rules.max_moves;
+  r.auto_reset = f->rules.auto_reset;
+  r.two_square = f->rules.two_square;
+  r.sampler = f->rules.sampler;
+  r.chasing = f->rules.chasing;
+  r.acting_obs = f->rules.acting_obs;
+  return r;
+}
+
 // A record as two 768-byte halves, 12 bytes per lane: every lane takes part
 // in both accesses, so no branch can skip one.  (A skipped access would leave
 // the compiler unsure which loads are still in flight, and it would then wait
@@ -376,12 +394,12 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
                                   (uint32_t)__builtin_amdgcn_readlane((int)ahead.z, kcur), 0u);
               return philox(make_uint4(uniform_u32(hdr_u32(R, kOffGameId)), uniform_u32(hdr_u32(R, kOffPly)),
                                        uniform_u32(hdr_u32(R, kOffEpisode)), 0u),
-                            a.rules.seed);
+                            args_fresh()->rules.seed);
             } else {
               return philox(make_uint4(gid, ply, ep, 0u), a.rules.seed);
             }
           };
-          const bool magnet = a.rules.sampler == kSamplerMagnet;
+          const bool magnet = (kAhead ? args_fresh()->rules.sampler : a.rules.sampler) == kSamplerMagnet;
           if (!NOMASK && a.mask)
             action = magnet ? (n == 0 ? -1 : sample_magnet(d[0], d[1], d[2], d[3], draw)) : sample_dests(d, n, draw);
           else
@@ -423,7 +441,7 @@ __attribute__((amdgpu_waves_per_eu(ENC == 1 ? 2 : ENC == 2 ? 3 : ENC == kEncNone
       if (MODE & kDoStep) {
         uint8_t* const hist = args_fresh()->hist;
         if (hist) store_record(hist + (hist_row + slot) * kRecordBytes, R);   // the state acted on
-        StepOut o = FAST ? fast_step_game(R, slab + kSlabScratch, slab + kSlabProbQ, a.rules, action, rg)
+        StepOut o = FAST ? fast_step_game(R, slab + kSlabScratch, slab + kSlabProbQ, kAhead ? rules_fresh() : a.rules, action, rg)
                          : step_game<(MODE & kStepFromInput) != 0>(R, slab + kSlabScratch, slab + kSlabProbQ,
                                                                     a.rules, action);
         const size_t row = (size_t)a.out_base + oi;
