@@ -563,6 +563,40 @@ def test_serving_results_same_alone_and_in_the_mix():
     eng.close()
 
 
+def test_serving_observations_by_slot():
+    """obs_by_slot = 1 (as the serving benchmark runs): a step request's
+    observations land at the pool slots its games occupy.  With a pool larger
+    than all requests together and every request there at the start, no slot
+    is reused, so the rows written are exactly the oracle's observations of the
+    step requests' input states (compared as a set of rows: which slot a game
+    takes is the loop's own choice), and the other rows keep their fill."""
+    seed, N, fill = 2, 256, 0x5A
+    reqs = [(E.REQ_STEP, 1, 20, 0, 0.0), (E.REQ_ROLLOUT, 3, 50, 20, 0.0), (E.REQ_STEP, 1, 13, 70, 0.0)]
+    total = 83
+    recs = serving_inputs(total)
+    eng = E.Engine(N, seed, k_battleless=100, max_moves=1000, auto_reset=False)
+    inp = torch.from_numpy(recs).cuda()
+    out = torch.zeros_like(inp)
+    pool = torch.full((N, 2, 488, 10, 10), fill, dtype=torch.uint8, device="cuda")
+    E.stratego_serve(eng.ctx, reqs, inp, out, pool, obs_by_slot=True, realtime=False)
+    assert eng.error() == (0, -1)
+    got = cpu(pool).reshape(N, -1)
+    written = got[(got != fill).any(axis=1)]
+    want = np.concatenate([
+        O.OracleEngine.from_records(recs[f:f + b], seed, k_battleless=100, max_moves=1000).ply(obs=True, mask=False)["obs"]
+        for kind, _, b, f, _ in reqs if kind == E.REQ_STEP]).reshape(33, -1)
+    assert len(written) == len(want) == 33
+    key = lambda a: sorted(r.tobytes() for r in a)
+    assert key(written) == key(want), "the observation rows written differ from the oracle's"
+    out_h = cpu(out)
+    for kind, plies, b, f, _ in reqs:
+        ref = O.OracleEngine.from_records(recs[f:f + b], seed, k_battleless=100, max_moves=1000)
+        for _ in range(plies):
+            ref.ply(obs=False, mask=False)
+        assert_same(f"request at row {f} vs oracle", out_h[f:f + b], ref.export())
+    eng.close()
+
+
 def test_serving_backfill_admits_smaller_requests_first():
     """Admission order with and without backfilling, on a 100-slot pool: a
     50-game request that cannot fit beside a running 90-game one holds back a
